@@ -1,0 +1,198 @@
+"""Pins of the oracle's energy update: finite-volume diffusion (Eq. 22-26), harmonic
+face conductivities (Eq. 25), isotropic gradients (Eq. 19), the latent term and RK4
+(Eq. 17-18, Eq. 27), and exact energy conservation."""
+import numpy as np
+import pytest
+
+from oracle import eos, lbm
+from paper_1812_10375_amd import scenarios as S
+
+EXACT = ("freeze_eos_T", "no_advection", "no_latent")
+
+
+def _sim(nx, ny, nh=0, rho=None, T=None, **kw):
+    sc = S.base_params(nx=nx, ny=ny, heater_rows=nh, **kw)
+    sc["rho0"] = np.full((ny, nx), S.RHO_L) if rho is None else rho
+    sc["T0"] = np.full((nh + ny, nx), S.T_SAT) if T is None else T
+    return lbm.OracleSim(sc), sc
+
+
+def test_fv_diffusion_telescopes_to_the_boundary_heat():
+    rng = np.random.default_rng(0)
+    nx, ny, nh = 7, 11, 3
+    rho = rng.uniform(0.38, 6.5, (ny, nx))
+    o, sc = _sim(nx, ny, nh, rho=rho, flags=EXACT, T_bottom=0.11, T_top=0.08)
+    Y = rng.uniform(0.08, 0.11, (nh + ny, nx))
+    K, flux = o.energy_rhs(Y)
+    rc = np.vstack([np.full((nh, nx), sc["rho_w"] * sc["cv_w"]), rho * sc["cv"]])
+    total = (rc * K).sum()
+    assert total == pytest.approx(flux[0] + flux[1], rel=1e-12, abs=1e-14)
+
+
+def test_fv_with_uniform_lambda_is_the_five_point_laplacian():
+    rng = np.random.default_rng(1)
+    nx, ny = 6, 9
+    o, sc = _sim(nx, ny, flags=EXACT)
+    Y = rng.uniform(0.09, 0.1, (ny, nx))
+    K, _ = o.energy_rhs(Y)
+    lap = np.roll(Y, 1, 1) + np.roll(Y, -1, 1) + np.roll(Y, 1, 0) + np.roll(Y, -1, 0) - 4 * Y
+    # lambda / (rho c_v) = k everywhere
+    assert K[1:-1] == pytest.approx(sc["k"] * lap[1:-1], rel=1e-11, abs=1e-16)
+
+
+def test_fv_steady_state_is_the_series_resistance_profile():
+    # 1-D column through heater and a random fluid density profile: the steady state of
+    # the FV scheme with harmonic faces is the series-resistance solution, with each
+    # Dirichlet ghost one spacing away through the conductivity of its neighbour.
+    rng = np.random.default_rng(2)
+    ny, nh = 20, 5
+    rho = rng.uniform(0.38, 6.5, (ny, 1))
+    o, sc = _sim(1, ny, nh, rho=rho, flags=EXACT, T_bottom=0.12, T_top=0.07, top_tbc="dirichlet")
+    lam = np.concatenate([np.full(nh, sc["lambda_w"]), rho[:, 0] * sc["cv"] * sc["k"]])
+    r_face = 0.5 * (1 / lam[:-1] + 1 / lam[1:])
+    R = 1 / lam[0] + r_face.sum() + 1 / lam[-1]
+    q = (sc["T_bottom"] - sc["T_top"]) / R
+    T = sc["T_bottom"] - q * (1 / lam[0] + np.concatenate([[0.0], np.cumsum(r_face)]))
+    K, flux = o.energy_rhs(T[:, None])
+    cvol = np.concatenate([np.full(nh, sc["rho_w"] * sc["cv_w"]), rho[:, 0] * sc["cv"]])
+    assert np.abs(K[:, 0] * cvol).max() < 1e-13 * q
+    assert flux[0] == pytest.approx(q, rel=1e-12)
+    assert flux[1] == pytest.approx(-q, rel=1e-12)
+
+
+def test_isotropic_gradient_symbol_in_x():
+    # Eq. 19 applied to sin(k x) returns sin(k) cos(k x) exactly.
+    nx, ny, m = 16, 6, 3
+    kx = 2 * np.pi * m / nx
+    x = np.arange(nx)
+    Y = np.ones((ny, 1)) * (0.095 + 0.001 * np.sin(kx * x))[None, :]
+    a, _ = _sim(nx, ny, flags=("no_latent",))
+    b, _ = _sim(nx, ny, flags=("no_latent", "no_advection"))
+    for o in (a, b):
+        o.set_field("ux", np.ones((ny, nx)))
+        o.set_field("uy", np.zeros((ny, nx)))
+    adv = a.energy_rhs(Y)[0] - b.energy_rhs(Y)[0]
+    expect = -0.001 * np.sin(kx) * np.cos(kx * x)[None, :] * np.ones((ny, 1))
+    assert adv[1:-1] == pytest.approx(expect[1:-1], abs=1e-15)   # rows off the walls
+
+
+def test_isotropic_gradient_exact_on_quadratic_in_y():
+    nx, ny = 5, 12
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    Y = 0.09 + 1e-3 * y + 2e-5 * y * y
+    a, _ = _sim(nx, ny, flags=("no_latent",))
+    b, _ = _sim(nx, ny, flags=("no_latent", "no_advection"))
+    for o in (a, b):
+        o.set_field("ux", np.zeros((ny, nx)))
+        o.set_field("uy", np.full((ny, nx), 0.7))
+    adv = a.energy_rhs(Y)[0] - b.energy_rhs(Y)[0]
+    assert adv[1:-1] == pytest.approx((-0.7 * (1e-3 + 4e-5 * y))[1:-1], rel=1e-10)
+
+
+def test_latent_term_uses_dpdT_and_divergence():
+    rng = np.random.default_rng(3)
+    nx, ny = 6, 10
+    rho = rng.uniform(0.5, 6.0, (ny, nx))
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    c = 2.5e-3
+    Y = rng.uniform(0.09, 0.1, (ny, nx))
+    a, sc = _sim(nx, ny, rho=rho, flags=("no_advection",))
+    b, _ = _sim(nx, ny, rho=rho, flags=("no_advection", "no_latent"))
+    for o in (a, b):
+        o.set_field("ux", np.zeros((ny, nx)))
+        o.set_field("uy", c * y)
+    lat = a.energy_rhs(Y)[0] - b.energy_rhs(Y)[0]
+    expect = -(Y / (rho * sc["cv"])) * eos.dp_dT(rho, Y, S.OMEGA) * c
+    assert lat[1:-1] == pytest.approx(expect[1:-1], rel=1e-10)
+
+
+def _affine_operator(o, n_nodes, shape):
+    zero = np.zeros(shape)
+    b, _ = o.energy_rhs(zero)
+    A = np.zeros((n_nodes, n_nodes))
+    for j in range(n_nodes):
+        e = np.zeros(n_nodes)
+        e[j] = 1.0
+        A[:, j] = (o.energy_rhs(e.reshape(shape))[0] - b).ravel()
+    return A, b.ravel()
+
+
+@pytest.mark.parametrize("n_sub", [1, 2, 3])
+def test_rk4_is_the_fourth_order_taylor_polynomial(n_sub):
+    # Without advection and latent heat K(T) = A T + b is affine; one RK4 step of size
+    # h applied to it is T + h K + h^2/2 A K + h^3/6 A^2 K + h^4/24 A^3 K (Eq. 18),
+    # and Eq. 27 repeats it n_sub times with h = 1/n_sub.
+    rng = np.random.default_rng(4)
+    nx, ny, nh = 2, 3, 1
+    rho = rng.uniform(0.5, 6.0, (ny, nx))
+    T0 = rng.uniform(0.09, 0.1, (nh + ny, nx))
+    o, _ = _sim(nx, ny, nh, rho=rho, T=T0, flags=EXACT, n_sub=n_sub, T_bottom=0.11, T_top=0.085)
+    A, b = _affine_operator(o, (nh + ny) * nx, T0.shape)
+    T = T0.ravel().copy()
+    h = 1.0 / n_sub
+    for _ in range(n_sub):
+        Kv = A @ T + b
+        T = T + h * Kv + h**2 / 2 * A @ Kv + h**3 / 6 * A @ A @ Kv + h**4 / 24 * A @ A @ A @ Kv
+    o.set_field("T", T0)
+    o.energy_update()
+    assert o.field("T").ravel() == pytest.approx(T, rel=1e-13)
+
+
+def test_exact_energy_balance_interface_conduction():
+    # Sec. 3.2 setting (stagnant, no latent heat): the stored-energy change equals the
+    # heat that crossed the two Dirichlet walls, to round-off, over 1000 steps.
+    sc = S.interface_conduction()
+    o = lbm.OracleSim(sc)
+    o.step(1000)
+    ob = o.observe()
+    q = ob["Q_bottom_cum"] + ob["Q_top_cum"]
+    assert ob["dE_cum"] == pytest.approx(q, rel=1e-12)
+    assert abs(ob["Q_bottom_cum"]) > 1.0
+
+
+def test_exact_energy_balance_with_conjugate_heater():
+    sc = S.pool_boiling(nx=16, ny=24, heater_rows=6, n_sites=1, min_spacing=4, steps=1)
+    sc["flags"] = EXACT
+    o = lbm.OracleSim(sc)
+    o.step(300)
+    ob = o.observe()
+    assert ob["dE_cum"] == pytest.approx(ob["Q_bottom_cum"] + ob["Q_top_cum"], rel=1e-12)
+    assert ob["Q_bottom_cum"] > 1e-3
+
+
+def _relaxed_interface(ny, nx=2, steps=20000):
+    """Density profile of a flat interface relaxed by the LB part itself (isothermal)."""
+    sc = S.interface_conduction(nx=nx, ny=ny)
+    sc["T_bottom"] = sc["T_top"] = S.T_SAT
+    o = lbm.OracleSim(sc)
+    o.step(steps)
+    return o.field("rho")
+
+
+@pytest.fixture(scope="module")
+def relaxed40():
+    return _relaxed_interface(40)
+
+
+def _steady_flux_difference(rho, flags):
+    # Sec. 3.2: walls held at T_h = 1 and T_l = 0, start from (T_h + T_l)/2, density
+    # frozen, iterate the energy update to steady state (40 slowest-mode e-foldings).
+    ny, nx = rho.shape
+    o, sc = _sim(nx, ny, rho=rho, flags=flags, T_bottom=1.0, T_top=0.0, T=np.full((ny, nx), 0.5))
+    for _ in range(int(40 * ny * ny / (np.pi**2 * sc["k"]))):
+        o.energy_update()
+    K, flux = o.energy_rhs(o.field("T"))
+    qh, ql = flux[0], -flux[1]
+    return 2 * abs(qh - ql) / (qh + ql)
+
+
+def test_steady_flux_difference_finite_volume(paper, relaxed40):
+    # Sec. 3.2: below 1e-10 with the finite-volume scheme
+    d = _steady_flux_difference(relaxed40, EXACT)
+    assert d < paper["flux_difference_fv_max"]["value"]
+
+
+def test_steady_flux_difference_isotropic(paper, relaxed40):
+    # Sec. 3.2: about 0.18 with the isotropic central scheme (Eq. 20-21)
+    d = _steady_flux_difference(relaxed40, EXACT + ("diff_isotropic",))
+    assert d == pytest.approx(paper["flux_difference_isotropic"]["value"], abs=0.01)
