@@ -1,0 +1,174 @@
+/*
+ * lbm_api.h -- C ABI of the MI355X (gfx950) hybrid thermal pseudo-potential lattice
+ * Boltzmann library, after Hu & Liu, "Study of boiling heat transfer on the wall with
+ * an improved hybrid lattice Boltzmann model" (arXiv:1812.10375).
+ *
+ * One call of lbm_step advances the coupled system of Sec. 2 by one lattice time step
+ * per step requested:
+ *   - D2Q9 MRT collision and streaming (Eq. 1-5) with the pseudo-potential interaction
+ *     force from the Peng-Robinson equation of state (Eq. 6, 7, 28), the Li-type forcing
+ *     term (Eq. 8), buoyancy (Eq. 9) and wall adhesion with nucleation sites (Eq. 10,
+ *     Sec. 4.2);
+ *   - the temperature equation (Eq. 17) by classical RK4 (Eq. 18) with `n_sub`
+ *     sub-steps (Eq. 27), finite-volume diffusion with harmonic-mean face
+ *     conductivities (Eq. 22-26), isotropic gradients (Eq. 19), through the fluid and a
+ *     conjugate heater below it (Sec. 4.2);
+ *   - diagnostics: mass, stored energy, heat through the bottom, top and heater surface,
+ *     and the running mean/variance of the bottom heat flux (Sec. 3.2, Sec. 4.3).
+ *
+ * Geometry.  Fluid nodes (x, y), 0 <= x < nx (periodic), 0 <= y < ny.  `heater_rows`
+ * solid rows lie below fluid row 0; temperature lives on heater and fluid rows (T row
+ * j = y + heater_rows).  The solid below fluid row 0 is a half-way bounce-back wall.
+ * The top is a wall, a constant-pressure opening or a convective outlet.
+ *
+ * Memory.  The caller owns all device memory and the HIP stream.  lbm_init carves the
+ * caller's workspace (lbm_workspace_bytes() bytes, 256-byte aligned device memory)
+ * and copies the initial fields into it; the library never allocates device memory.
+ * Host arrays passed in are copied before the call returns.  A context is used by one
+ * host thread at a time.
+ *
+ * Errors.  Every entry point returns LBM_OK (0) or a negative status.  Argument errors
+ * are reported at once.  Errors found on the device (non-finite values, density <= 0,
+ * 1 - b rho <= 0, or a negative radicand under the square root of Eq. 7) are sticky:
+ * lbm_observe reports LBM_ENONFINITE with the first bad step, and lbm_step refuses to
+ * run afterwards (LBM_ESTATE).
+ */
+#ifndef LBM_API_H
+#define LBM_API_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* bad argument or configuration                        */
+  LBM_ENOMEM = -2,     /* workspace smaller than lbm_workspace_bytes()         */
+  LBM_EHIP = -3,       /* a HIP runtime call failed                            */
+  LBM_ENONFINITE = -4, /* the device flagged a bad state (see above)           */
+  LBM_ESTATE = -5      /* call not allowed in the context's current state      */
+};
+
+enum { LBM_F32 = 0, LBM_F64 = 1 }; /* storage and arithmetic type of the fields   */
+enum { LBM_TOP_WALL = 0, LBM_TOP_CONST_PRESSURE = 1, LBM_TOP_CONVECTIVE = 2 };
+enum { LBM_TBC_DIRICHLET = 0, LBM_TBC_FLUX = 1, LBM_TBC_ZERO_GRAD = 2 };
+enum {
+  LBM_FREEZE_EOS_T = 1u,   /* EOS of Eq. 7 evaluated at T_sat (Sec. 3.2)          */
+  LBM_NO_ADVECTION = 2u,   /* drop -u.grad T from Eq. 17                          */
+  LBM_NO_LATENT = 4u,      /* drop the (dp/dT)_v div(u) term from Eq. 17          */
+  LBM_DIFF_ISOTROPIC = 8u  /* diffusion by Eq. 20-21 (comparison scheme)          */
+};
+
+/*
+ * Configuration.  Set struct_size = sizeof(lbm_config) and abi_version =
+ * LBM_ABI_VERSION.  Units are lattice units (c = dx = dt = 1).
+ *   nx, ny, heater_rows   lattice size; nx, ny >= 1 (ny >= 2 with an open top)
+ *   n_sub                 N of Eq. 27 (energy sub-steps per LB step), >= 1
+ *   precision             LBM_F32 or LBM_F64 (the Peng-Robinson EOS of Eq. 7/28 and all
+ *                         reductions are FP64 in both)
+ *   a, b, R, omega        Peng-Robinson constants (Eq. 28, Sec. 3.1)
+ *   T_sat                 saturation temperature (EOS temperature under FREEZE_EOS_T)
+ *   G, sigma              Eq. 7 interaction strength (< 0) and Eq. 8 parameter
+ *   tau_l, tau_v          viscous relaxation times of liquid and vapour (nu = (tau-1/2)/3);
+ *                         tau varies linearly in density between rho_v and rho_l
+ *   s_e, s_zeta, s_q      the other relaxation rates of Eq. 3
+ *   rho_l, rho_v          coexistence densities (tau interpolation, constant-pressure top)
+ *   cv, k                 fluid heat capacity and diffusivity: lambda = rho cv k
+ *   rho_w, cv_w, lambda_w heater density, heat capacity, conductivity (Sec. 4.2)
+ *   g                     gravity magnitude, acting along -y (Eq. 9)
+ *   T_bottom, q_bottom    bottom thermal boundary: temperature of the Dirichlet ghost row
+ *                         one spacing below the lowest T row, or heat flux into the domain
+ *   T_top                 top Dirichlet temperature (bottom_tbc/top_tbc select the kind)
+ *   Gw0, Gw_top           wall strengths of Eq. 10 at the bottom wall and a top wall
+ *   n_sites, site_*       nucleation sites (Sec. 4.2): centre x, width, minimum strength;
+ *                         host arrays of n_sites doubles (may be NULL when n_sites = 0)
+ */
+typedef struct {
+  uint32_t struct_size, abi_version;
+  int32_t nx, ny, heater_rows, n_sub;
+  int32_t precision, top_bc, bottom_tbc, top_tbc;
+  uint32_t flags;
+  double a, b, R, omega, T_sat, G, sigma;
+  double tau_l, tau_v, s_e, s_zeta, s_q;
+  double rho_l, rho_v;
+  double cv, k, rho_w, cv_w, lambda_w;
+  double g;
+  double T_bottom, T_top, q_bottom;
+  double Gw0, Gw_top;
+  int32_t n_sites;
+  const double *site_xc, *site_width, *site_gmin;
+} lbm_config;
+
+/*
+ * Observation after the last completed step (all FP64):
+ *   mass        sum of rho over the fluid, state after the step
+ *   energy      sum of (rho c_v) T over heater and fluid (rho of the step's collision)
+ *   rho_ave     domain-mean density that the next step's buoyancy uses (Eq. 9)
+ *   q_bottom    heat entering through the bottom boundary per unit length and time,
+ *               last step (RK-weighted over the Eq. 18 stages); q_bottom_mean/_var are
+ *               its running mean and population variance over all steps
+ *   q_surface   same through the heater/fluid surface (= q_bottom without a heater)
+ *   *_cum       cumulative heat through bottom, top and surface; dE_cum is the
+ *               cumulative sum of (rho c_v)(T^{n+1} - T^n)
+ *   max_speed   largest |u| of the last collision
+ */
+typedef struct {
+  int64_t step;
+  double mass, energy, rho_ave;
+  double q_bottom, q_bottom_mean, q_bottom_var, q_surface;
+  double Q_bottom_cum, Q_top_cum, Q_surface_cum, dE_cum, max_speed;
+  int32_t error_flags; /* LBM_ERR_* bits */
+  int64_t first_bad_step;
+} lbm_obs;
+
+enum { LBM_ERR_RHO = 1, LBM_ERR_COVOLUME = 2, LBM_ERR_RADICAND = 4, LBM_ERR_NONFINITE = 8 };
+
+/* Fields for lbm_read_field / lbm_write_field; element type is the context's precision.
+ *   LBM_FIELD_F    9 x ny x nx pre-collision populations f^n (x fastest)   read/write
+ *   LBM_FIELD_T    (heater_rows + ny) x nx temperature                     read/write
+ *   LBM_FIELD_RHO  ny x nx density of the last collision                   read
+ *   LBM_FIELD_UX/UY ny x nx Eq. 5 velocity of the last collision           read
+ *   LBM_FIELD_GW   nx wall strength of each column of the bottom wall      read       */
+enum { LBM_FIELD_F = 0, LBM_FIELD_RHO = 1, LBM_FIELD_UX = 2, LBM_FIELD_UY = 3, LBM_FIELD_T = 4,
+       LBM_FIELD_GW = 10 };
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Bytes of device workspace lbm_init needs for cfg; 0 if cfg is invalid.  Host only. */
+size_t lbm_workspace_bytes(const lbm_config *cfg);
+
+/* Create a context on the current HIP device.  d_workspace: device pointer to
+ * ws_bytes bytes (>= lbm_workspace_bytes), 256-byte aligned, owned by the caller and
+ * borrowed until lbm_destroy.  hip_stream: hipStream_t to enqueue on (NULL = default).
+ * rho0_host: ny*nx initial densities (the populations start at equilibrium at rest);
+ * T0_host: (heater_rows+ny)*nx initial temperatures.  Synchronises the stream. */
+int lbm_init(const lbm_config *cfg, void *d_workspace, size_t ws_bytes, void *hip_stream,
+             const double *rho0_host, const double *T0_host, lbm_ctx **out);
+
+/* Enqueue nsteps (>= 0) complete steps on the context's stream; never synchronises. */
+int lbm_step(lbm_ctx *h, int64_t nsteps);
+
+/* Synchronise the stream and fill *out; LBM_ENONFINITE if the device flagged an error. */
+int lbm_observe(lbm_ctx *h, lbm_obs *out);
+
+/* Copy a field to dst (host or device memory of `bytes` bytes, which must equal the
+ * field's size).  Synchronises the stream for host destinations. */
+int lbm_read_field(lbm_ctx *h, int field, void *dst, size_t bytes, int dst_is_device);
+
+/* Overwrite the populations (LBM_FIELD_F, pre-collision) or the temperature. */
+int lbm_write_field(lbm_ctx *h, int field, const void *src, size_t bytes, int src_is_device);
+
+/* Release the host-side context (the workspace stays the caller's). */
+int lbm_destroy(lbm_ctx *h);
+
+/* Static description of a status code. */
+const char *lbm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

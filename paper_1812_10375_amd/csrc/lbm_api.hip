@@ -1,0 +1,326 @@
+// lbm_api.hip -- host side of the C ABI declared in include/lbm_api.h: validation,
+// workspace carving, the wall profile, and the entry points.  Kernel launches live in
+// lbm_f32.hip / lbm_f64.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbm_api.h"
+#include "lbm_ctx.hpp"
+
+using lbmk::DevDiag;
+using lbmk::KParams;
+using namespace lbmh;
+
+namespace {
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool valid_config(const lbm_config* c) {
+  if (!c) return false;
+  if (c->struct_size != sizeof(lbm_config) || c->abi_version != LBM_ABI_VERSION) return false;
+  if (c->nx < 1 || c->ny < 1 || c->heater_rows < 0 || c->n_sub < 1) return false;
+  if (c->nx > (1 << 20) || c->ny > (1 << 20) || c->heater_rows > (1 << 20)) return false;
+  if ((double)c->nx * (double)(c->ny + c->heater_rows) > 4.0e9) return false;
+  if (c->precision != LBM_F32 && c->precision != LBM_F64) return false;
+  if (c->top_bc < LBM_TOP_WALL || c->top_bc > LBM_TOP_CONVECTIVE) return false;
+  if (c->top_bc != LBM_TOP_WALL && c->ny < 2) return false;
+  if (c->bottom_tbc != LBM_TBC_DIRICHLET && c->bottom_tbc != LBM_TBC_FLUX) return false;
+  if (c->top_tbc != LBM_TBC_DIRICHLET && c->top_tbc != LBM_TBC_ZERO_GRAD) return false;
+  if (c->flags & ~15u) return false;
+  if (!(c->a > 0 && c->b > 0 && c->R > 0 && c->T_sat > 0 && c->G < 0)) return false;
+  if (!(c->tau_l > 0.5 && c->tau_v > 0.5 && c->s_e > 0 && c->s_e < 2 && c->s_zeta > 0 &&
+        c->s_zeta < 2 && c->s_q > 0 && c->s_q < 2))
+    return false;
+  if (!(c->rho_l > c->rho_v && c->rho_v > 0)) return false;
+  if (!(c->cv > 0 && c->k > 0)) return false;
+  if (c->heater_rows > 0 && !(c->rho_w > 0 && c->cv_w > 0 && c->lambda_w > 0)) return false;
+  if (c->n_sites < 0) return false;
+  if (c->n_sites > 0 && (!c->site_xc || !c->site_width || !c->site_gmin)) return false;
+  const double vals[] = {c->a, c->b, c->R, c->omega, c->T_sat, c->G, c->sigma, c->g,
+                         c->T_bottom, c->T_top, c->q_bottom, c->Gw0, c->Gw_top};
+  for (double v : vals)
+    if (!std::isfinite(v)) return false;
+  return true;
+}
+
+void grids(const lbm_config* c, int* ntxL, int* ntyL, int* ntxE, int* ntyE) {
+  const bool f64 = c->precision == LBM_F64;
+  const int ty = f64 ? TY_F64 : TY_F32;
+  const int tx = (f64 ? W3_F64 : W3_F32) - 6, tye = H3_E - 6;
+  const int nT = c->heater_rows + c->ny;
+  *ntxL = (c->nx + 63) / 64;
+  *ntyL = (c->ny + ty - 1) / ty;
+  *ntxE = (c->nx + tx - 1) / tx;
+  *ntyE = (nT + tye - 1) / tye;
+}
+
+Layout layout(const lbm_config* c) {
+  Layout L{};
+  const size_t R = c->precision == LBM_F64 ? 8 : 4;
+  const size_t nx = c->nx, ny = c->ny, nT = (size_t)c->heater_rows + ny;
+  int ntxL, ntyL, ntxE, ntyE;
+  grids(c, &ntxL, &ntyL, &ntxE, &ntyE);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.f[0] = take(9 * nx * ny * R);
+  L.f[1] = take(9 * nx * ny * R);
+  L.T[0] = take(nT * nx * R);
+  L.T[1] = take(nT * nx * R);
+  L.rho = take(nx * ny * R);
+  L.ux = take(nx * ny * R);
+  L.uy = take(nx * ny * R);
+  L.topin = take(3 * nx * R);
+  L.gw = take(nx * R);
+  L.partL = take((size_t)ntxL * ntyL * 2 * sizeof(double));
+  L.partE = take((size_t)ntxE * ntyE * 5 * sizeof(double));
+  L.diag = take(sizeof(DevDiag));
+  L.total = off;
+  return L;
+}
+
+// Wall strength of each bottom-wall column (Eq. 10 with the nucleation sites of
+// Sec. 4.2): a site of width W centred at xc lowers G_w linearly from Gw0 at its
+// edges to its minimum at the centre; column c is centred at c + 1/2; x is periodic.
+std::vector<double> wall_profile(const lbm_config* c) {
+  std::vector<double> gw(c->nx, c->Gw0);
+  for (int s = 0; s < c->n_sites; ++s) {
+    const double half = 0.5 * c->site_width[s], gmin = c->site_gmin[s], xc = c->site_xc[s];
+    for (int x = 0; x < c->nx; ++x) {
+      double d = (x + 0.5) - xc;
+      d -= c->nx * std::floor(d / c->nx + 0.5);
+      const double ad = std::fabs(d);
+      if (ad < half) gw[x] = std::min(gw[x], gmin + (c->Gw0 - gmin) * (ad / half));
+    }
+  }
+  return gw;
+}
+
+KParams make_params(const lbm_config* c) {
+  KParams P{};
+  P.nx = c->nx;
+  P.ny = c->ny;
+  P.nh = c->heater_rows;
+  P.nT = c->heater_rows + c->ny;
+  P.flags = (int)c->flags;
+  P.top_bc = c->top_bc;
+  P.bottom_tbc = c->bottom_tbc;
+  P.top_tbc = c->top_tbc;
+  grids(c, &P.ntxL, &P.ntyL, &P.ntxE, &P.ntyE);
+  P.nblkL = P.ntxL * P.ntyL;
+  P.nblkE = P.ntxE * P.ntyE;
+  P.tyL = c->precision == LBM_F64 ? TY_F64 : TY_F32;
+  // Eq. 28 and Sec. 3.1: a = 0.45724 R^2 Tc^2 / pc, b = 0.0778 R Tc / pc
+  const double Tc = (c->a / c->b) * (0.0778 / 0.45724) / c->R;
+  const double kap = 0.37464 + 1.54226 * c->omega - 0.26992 * c->omega * c->omega;
+  P.a = c->a;
+  P.b = c->b;
+  P.R = c->R;
+  P.G = c->G;
+  P.Tc = Tc;
+  P.inv_Tc = 1.0 / Tc;
+  P.kappa = kap;
+  const double ssat = 1.0 + kap * (1.0 - std::sqrt(c->T_sat / Tc));
+  P.phi_sat = ssat * ssat;
+  P.T_sat = c->T_sat;
+  P.inv3 = 1.0 / 3.0;
+  P.rho_l = c->rho_l;
+  P.rho_v = c->rho_v;
+  P.inv_drho = 1.0 / (c->rho_l - c->rho_v);
+  P.tau_v = c->tau_v;
+  P.dtau = c->tau_l - c->tau_v;
+  P.s_e = c->s_e;
+  P.s_z = c->s_zeta;
+  P.s_q = c->s_q;
+  P.c_e = 1.0 - 0.5 * c->s_e;
+  P.c_z = 1.0 - 0.5 * c->s_zeta;
+  P.c_q = 1.0 - 0.5 * c->s_q;
+  // Eq. 8 sigma terms: 12 sigma |F_m|^2 / (psi^2 (tau - 1/2)) with tau = 1/s
+  P.sig_e = 12.0 * c->sigma / (1.0 / c->s_e - 0.5);
+  P.sig_z = 12.0 * c->sigma / (1.0 / c->s_zeta - 0.5);
+  P.g = c->g;
+  P.Gw_top = c->Gw_top;
+  P.cv = c->cv;
+  P.k = c->k;
+  P.cvk = c->cv * c->k;
+  P.sigma = c->sigma;
+  P.tau_l = c->tau_l;
+  P.s_e_raw = c->s_e;
+  P.s_z_raw = c->s_zeta;
+  P.rcw = c->rho_w * c->cv_w;
+  P.lambda_w = c->lambda_w;
+  P.T_bottom = c->T_bottom;
+  P.T_top = c->T_top;
+  P.q_bottom = c->q_bottom;
+  return P;
+}
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_config* cfg) {
+  if (!valid_config(cfg)) return 0;
+  return layout(cfg).total;
+}
+
+int lbm_init(const lbm_config* cfg, void* d_workspace, size_t ws_bytes, void* hip_stream,
+             const double* rho0_host, const double* T0_host, lbm_ctx** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  if (!valid_config(cfg) || !d_workspace || !rho0_host || !T0_host) return LBM_EINVAL;
+  if (reinterpret_cast<uintptr_t>(d_workspace) & 255) return LBM_EINVAL;
+  Layout L = layout(cfg);
+  if (ws_bytes < L.total) return LBM_ENOMEM;
+  lbm_ctx* h = new (std::nothrow) lbm_ctx();
+  if (!h) return LBM_ENOMEM;
+  h->cfg = *cfg;
+  h->cfg.n_sites = 0;  // the site table is consumed here (wall profile); do not keep host pointers
+  h->cfg.site_xc = h->cfg.site_width = h->cfg.site_gmin = nullptr;
+  h->P = make_params(cfg);
+  h->L = L;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  h->ws = reinterpret_cast<char*>(d_workspace);
+  h->fcur = 0;
+  h->tcur = 0;
+  h->step = 0;
+  h->bad = false;
+  const std::vector<double> gw = wall_profile(cfg);
+  int rc = cfg->precision == LBM_F64 ? init_fields<double>(h, rho0_host, T0_host, gw.data())
+                                     : init_fields<float>(h, rho0_host, T0_host, gw.data());
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* h, int64_t nsteps) {
+  if (!h || nsteps < 0) return LBM_EINVAL;
+  if (h->bad) return LBM_ESTATE;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    if (h->cfg.precision == LBM_F64) step_once<double>(h);
+    else step_once<float>(h);
+  }
+  return hip_ok(hipGetLastError());
+}
+
+int lbm_observe(lbm_ctx* h, lbm_obs* out) {
+  if (!h || !out) return LBM_EINVAL;
+  const Layout& L = h->L;
+  DevDiag* dd = h->at<DevDiag>(L.diag);
+  if (h->cfg.precision == LBM_F64) finish_reductions<double>(h);
+  else finish_reductions<float>(h);
+  DevDiag d;
+  if (hipMemcpyAsync(&d, dd, sizeof(d), hipMemcpyDeviceToHost, h->stream) != hipSuccess) return LBM_EHIP;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return LBM_EHIP;
+  std::memset(out, 0, sizeof(*out));
+  out->step = h->step;
+  out->mass = d.mass;
+  out->energy = d.energy;
+  out->rho_ave = d.rho_ave;
+  out->q_bottom = d.q_bottom;
+  out->q_bottom_mean = d.q_mean;
+  out->q_bottom_var = d.nred > 0 ? d.q_m2 / (double)d.nred : 0.0;
+  out->q_surface = d.q_surface;
+  out->Q_bottom_cum = d.Q_bottom_cum;
+  out->Q_top_cum = d.Q_top_cum;
+  out->Q_surface_cum = d.Q_surface_cum;
+  out->dE_cum = d.dE_cum;
+  out->max_speed = d.max_speed;
+  out->error_flags = (int32_t)d.err;
+  out->first_bad_step = d.err ? (int64_t)d.first_bad : -1;
+  if (d.err) {
+    h->bad = true;
+    return LBM_ENONFINITE;
+  }
+  return LBM_OK;
+}
+
+int lbm_read_field(lbm_ctx* h, int field, void* dst, size_t bytes, int dst_is_device) {
+  if (!h || !dst) return LBM_EINVAL;
+  const Layout& L = h->L;
+  const size_t R = h->cfg.precision == LBM_F64 ? 8 : 4;
+  const size_t nx = h->cfg.nx, ny = h->cfg.ny, N = nx * ny;
+  const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const void* src = nullptr;
+  size_t need = 0;
+  switch (field) {
+    case LBM_FIELD_RHO: src = h->ws + L.rho; need = N * R; break;
+    case LBM_FIELD_UX: src = h->ws + L.ux; need = N * R; break;
+    case LBM_FIELD_UY: src = h->ws + L.uy; need = N * R; break;
+    case LBM_FIELD_T: src = h->ws + L.T[h->tcur]; need = (N + nx * h->cfg.heater_rows) * R; break;
+    case LBM_FIELD_GW: src = h->ws + L.gw; need = nx * R; break;
+    case LBM_FIELD_F: {
+      need = 9 * N * R;
+      if (bytes != need) return LBM_EINVAL;
+      // pull f^n into the spare population buffer, then copy it out
+      void* spare = h->ws + L.f[1 - h->fcur];
+      if (R == 8) gather_populations<double>(h, (double*)spare);
+      else gather_populations<float>(h, (float*)spare);
+      src = spare;
+      break;
+    }
+    default: return LBM_EINVAL;
+  }
+  if (bytes != need) return LBM_EINVAL;
+  if (hipMemcpyAsync(dst, src, need, kind, h->stream) != hipSuccess) return LBM_EHIP;
+  if (!dst_is_device && hipStreamSynchronize(h->stream) != hipSuccess) return LBM_EHIP;
+  return hip_ok(hipGetLastError());
+}
+
+int lbm_write_field(lbm_ctx* h, int field, const void* src, size_t bytes, int src_is_device) {
+  if (!h || !src) return LBM_EINVAL;
+  const Layout& L = h->L;
+  const size_t R = h->cfg.precision == LBM_F64 ? 8 : 4;
+  const size_t nx = h->cfg.nx, ny = h->cfg.ny, N = nx * ny;
+  const hipMemcpyKind kind = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (field == LBM_FIELD_T) {
+    const size_t need = (N + nx * h->cfg.heater_rows) * R;
+    if (bytes != need) return LBM_EINVAL;
+    if (hipMemcpyAsync(h->ws + L.T[h->tcur], src, need, kind, h->stream) != hipSuccess) return LBM_EHIP;
+    return hip_ok(hipStreamSynchronize(h->stream));
+  }
+  if (field == LBM_FIELD_F) {
+    const size_t need = 9 * N * R;
+    if (bytes != need) return LBM_EINVAL;
+    void* spare = h->ws + L.f[1 - h->fcur];
+    if (hipMemcpyAsync(spare, src, need, kind, h->stream) != hipSuccess) return LBM_EHIP;
+    int rc = R == 8 ? scatter_state<double>(h, (const double*)spare, 0)
+                    : scatter_state<float>(h, (const float*)spare, 0);
+    if (rc) return rc;
+    return hip_ok(hipStreamSynchronize(h->stream));
+  }
+  return LBM_EINVAL;
+}
+
+int lbm_destroy(lbm_ctx* h) {
+  if (!h) return LBM_EINVAL;
+  delete h;
+  return LBM_OK;
+}
+
+const char* lbm_strerror(int status) {
+  switch (status) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument or configuration";
+    case LBM_ENOMEM: return "workspace too small";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_ENONFINITE: return "device flagged a non-finite or unphysical state";
+    case LBM_ESTATE: return "call not allowed in the current state";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// lbm_launch.hpp -- kernel launches of one precision.  Included by lbm_f32.hip and
+// lbm_f64.hip, which instantiate it for float and double.
+#pragma once
+#include <algorithm>
+#include <vector>
+
+#include "lbm_ctx.hpp"
+#include "lbm_kernels.hpp"
+
+namespace lbmh {
+
+using lbmk::DevDiag;
+using lbmk::KParams;
+using lbmk::NT;
+
+// One lattice step: k_collide, then k_energy once per energy sub-step (Eq. 27).
+template <typename real>
+void step_once(lbm_ctx* h) {
+  const KParams& P = h->P;
+  const Layout& L = h->L;
+  constexpr bool f64 = sizeof(real) == 8;
+  real* fs = h->at<real>(L.f[h->fcur]);
+  real* fd = h->at<real>(L.f[1 - h->fcur]);
+  real* topin = h->at<real>(L.topin);
+  real* rho = h->at<real>(L.rho);
+  real* ux = h->at<real>(L.ux);
+  real* uy = h->at<real>(L.uy);
+  double* partL = h->at<double>(L.partL);
+  double* partE = h->at<double>(L.partE);
+  DevDiag* diag = h->at<DevDiag>(L.diag);
+  const real* gw = h->at<real>(L.gw);
+  const real* Tc = h->at<real>(L.T[h->tcur]);
+  hipLaunchKernelGGL((lbmk::k_collide<real, f64 ? TY_F64 : TY_F32>), dim3(P.nblkL), dim3(NT), 0,
+                     h->stream, P, fs, fd, topin, Tc, gw, rho, ux, uy, partL, partE, diag,
+                     (long long)h->step);
+  const double dt = 1.0 / h->cfg.n_sub;
+  const bool iso = (h->cfg.flags & LBM_DIFF_ISOTROPIC) != 0;
+  constexpr int W3 = f64 ? W3_F64 : W3_F32;
+  for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
+    const real* Tin = h->at<real>(L.T[h->tcur]);
+    real* Tout = h->at<real>(L.T[1 - h->tcur]);
+    if (iso)
+      hipLaunchKernelGGL((lbmk::k_energy<real, W3, H3_E, true>), dim3(P.nblkE), dim3(NT), 0,
+                         h->stream, P, Tin, Tout, rho, ux, uy, partE, fd, topin, partL, diag, sub,
+                         dt, (long long)h->step);
+    else
+      hipLaunchKernelGGL((lbmk::k_energy<real, W3, H3_E, false>), dim3(P.nblkE), dim3(NT), 0,
+                         h->stream, P, Tin, Tout, rho, ux, uy, partE, fd, topin, partL, diag, sub,
+                         dt, (long long)h->step);
+    h->tcur = 1 - h->tcur;
+  }
+  h->fcur = 1 - h->fcur;
+  h->step += 1;
+}
+
+// Finish any pending reductions (mass after a scatter, energy after a step).
+template <typename real>
+void finish_reductions(lbm_ctx* h) {
+  const Layout& L = h->L;
+  hipLaunchKernelGGL((lbmk::k_finish<real>), dim3(1), dim3(NT), 0, h->stream, h->P,
+                     h->at<double>(L.partL), h->at<double>(L.partE), h->at<real>(L.f[h->fcur]),
+                     h->at<real>(L.topin), h->at<real>(L.ux), h->at<real>(L.uy),
+                     h->at<DevDiag>(L.diag));
+}
+
+// Store pre-collision populations (or the equilibrium at rest of a density field)
+// as the current state, and reduce its mass.
+template <typename real>
+int scatter_state(lbm_ctx* h, const real* src, int src_is_rho) {
+  const Layout& L = h->L;
+  hipLaunchKernelGGL((lbmk::k_scatter<real>), dim3(h->P.nblkL), dim3(NT), 0, h->stream, h->P, src,
+                     src_is_rho, h->at<real>(L.f[h->fcur]), h->at<real>(L.topin),
+                     h->at<double>(L.partL), h->at<DevDiag>(L.diag));
+  finish_reductions<real>(h);
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+
+template <typename real>
+void gather_populations(lbm_ctx* h, real* out) {
+  const Layout& L = h->L;
+  const size_t N = (size_t)h->P.nx * h->P.ny;
+  const int grid = (int)std::min<size_t>((N + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL((lbmk::k_gather<real>), dim3(grid), dim3(NT), 0, h->stream, h->P,
+                     h->at<real>(L.f[h->fcur]), h->at<real>(L.topin), out);
+}
+
+template <typename real>
+static int copy_converted(lbm_ctx* h, const double* host, real* dev, size_t n) {
+  // host FP64 -> device real; synchronised so the staging vector outlives the copy
+  std::vector<real> tmp(n);
+  for (size_t i = 0; i < n; ++i) tmp[i] = (real)host[i];
+  if (hipMemcpyAsync(dev, tmp.data(), n * sizeof(real), hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    return LBM_EHIP;
+  return hipStreamSynchronize(h->stream) == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+
+template <typename real>
+int init_fields(lbm_ctx* h, const double* rho0, const double* T0, const double* gw) {
+  const Layout& L = h->L;
+  const size_t nx = h->P.nx, N = nx * h->P.ny, NTn = nx * h->P.nT;
+  int rc;
+  if ((rc = copy_converted<real>(h, T0, h->at<real>(L.T[0]), NTn))) return rc;
+  if ((rc = copy_converted<real>(h, rho0, h->at<real>(L.rho), N))) return rc;
+  if ((rc = copy_converted<real>(h, gw, h->at<real>(L.gw), nx))) return rc;
+  if (hipMemsetAsync(h->at<real>(L.ux), 0, N * sizeof(real), h->stream) != hipSuccess) return LBM_EHIP;
+  if (hipMemsetAsync(h->at<real>(L.uy), 0, N * sizeof(real), h->stream) != hipSuccess) return LBM_EHIP;
+  if (hipMemsetAsync(h->at<real>(L.topin), 0, 3 * nx * sizeof(real), h->stream) != hipSuccess) return LBM_EHIP;
+  DevDiag d{};
+  d.first_bad = ~0ull;
+  if (hipMemcpyAsync(h->at<DevDiag>(L.diag), &d, sizeof(d), hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    return LBM_EHIP;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return LBM_EHIP;
+  if ((rc = scatter_state<real>(h, h->at<real>(L.rho), 1))) return rc;
+  return hipStreamSynchronize(h->stream) == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+
+}  // namespace lbmh
+
+#define LBM_INSTANTIATE(T)                                                                  \
+  namespace lbmh {                                                                          \
+  template void step_once<T>(lbm_ctx*);                                                     \
+  template int scatter_state<T>(lbm_ctx*, const T*, int);                                   \
+  template void finish_reductions<T>(lbm_ctx*);                                             \
+  template void gather_populations<T>(lbm_ctx*, T*);                                        \
+  template int init_fields<T>(lbm_ctx*, const double*, const double*, const double*);       \
+  }

@@ -1,0 +1,190 @@
+"""Python binding of the gfx950 library (``include/lbm_api.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``liblbm_hip.so``.  PyTorch provides the device workspace and the stream.  There is
+no CPU fallback: without the built library (or without a GPU) construction fails.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
+
+F32, F64 = 0, 1
+TOP_BC = {"wall": 0, "const_pressure": 1, "convective": 2}
+TBC = {"dirichlet": 0, "flux": 1, "zero_grad": 2}
+FLAG_BITS = {"freeze_eos_T": 1, "no_advection": 2, "no_latent": 4, "diff_isotropic": 8}
+FIELDS = {"f": 0, "rho": 1, "ux": 2, "uy": 3, "T": 4, "Gw": 10}
+STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
+          -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
+ABI_VERSION = 1
+
+
+class LbmConfig(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("abi_version", C.c_uint32),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("heater_rows", C.c_int32), ("n_sub", C.c_int32),
+                ("precision", C.c_int32), ("top_bc", C.c_int32), ("bottom_tbc", C.c_int32),
+                ("top_tbc", C.c_int32), ("flags", C.c_uint32)] + [
+        (n, C.c_double) for n in (
+            "a", "b", "R", "omega", "T_sat", "G", "sigma", "tau_l", "tau_v", "s_e", "s_zeta", "s_q",
+            "rho_l", "rho_v", "cv", "k", "rho_w", "cv_w", "lambda_w", "g", "T_bottom", "T_top",
+            "q_bottom", "Gw0", "Gw_top")] + [
+        ("n_sites", C.c_int32), ("site_xc", C.POINTER(C.c_double)),
+        ("site_width", C.POINTER(C.c_double)), ("site_gmin", C.POINTER(C.c_double))]
+
+
+class LbmObs(C.Structure):
+    _fields_ = [("step", C.c_int64)] + [
+        (n, C.c_double) for n in (
+            "mass", "energy", "rho_ave", "q_bottom", "q_bottom_mean", "q_bottom_var", "q_surface",
+            "Q_bottom_cum", "Q_top_cum", "Q_surface_cum", "dE_cum", "max_speed")] + [
+        ("error_flags", C.c_int32), ("first_bad_step", C.c_int64)]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__("%s failed: %s (%d)" % (what, STATUS.get(status, "?"), status))
+        self.status = status
+
+
+_lib = None
+
+
+def library():
+    """The loaded C-ABI library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblbm_hip.so is not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        cfgp = C.POINTER(LbmConfig)
+        vp = C.c_void_p
+        dp = C.POINTER(C.c_double)
+        L.lbm_workspace_bytes.restype = C.c_size_t
+        L.lbm_workspace_bytes.argtypes = [cfgp]
+        L.lbm_init.restype = C.c_int
+        L.lbm_init.argtypes = [cfgp, vp, C.c_size_t, vp, dp, dp, C.POINTER(vp)]
+        L.lbm_step.restype = C.c_int
+        L.lbm_step.argtypes = [vp, C.c_int64]
+        L.lbm_observe.restype = C.c_int
+        L.lbm_observe.argtypes = [vp, C.POINTER(LbmObs)]
+        L.lbm_read_field.restype = C.c_int
+        L.lbm_read_field.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
+        L.lbm_write_field.restype = C.c_int
+        L.lbm_write_field.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
+        L.lbm_destroy.restype = C.c_int
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_strerror.restype = C.c_char_p
+        L.lbm_strerror.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_config(sc):
+    """Marshal a scenario dictionary into lbm_config (returns it and the arrays it points to)."""
+    c = LbmConfig()
+    c.struct_size = C.sizeof(LbmConfig)
+    c.abi_version = ABI_VERSION
+    c.nx, c.ny, c.heater_rows = sc["nx"], sc["ny"], sc["heater_rows"]
+    c.n_sub = sc.get("n_sub", 1)
+    c.precision = F64 if sc.get("precision", "f64") == "f64" else F32
+    c.top_bc = TOP_BC[sc["top_bc"]]
+    c.bottom_tbc = TBC[sc["bottom_tbc"]]
+    c.top_tbc = TBC[sc["top_tbc"]]
+    c.flags = sum(FLAG_BITS[f] for f in sc.get("flags", ()))
+    for n in ("a", "b", "R", "omega", "T_sat", "G", "sigma", "tau_l", "tau_v", "s_e", "s_zeta",
+              "s_q", "rho_l", "rho_v", "cv", "k", "rho_w", "cv_w", "lambda_w", "g", "T_bottom",
+              "T_top", "q_bottom", "Gw0", "Gw_top"):
+        setattr(c, n, float(sc[n]))
+    sites = np.asarray(sc.get("sites", np.zeros((0, 3))), dtype=np.float64).reshape(-1, 3)
+    keep = [np.ascontiguousarray(sites[:, k]) for k in range(3)]
+    c.n_sites = sites.shape[0]
+    c.site_xc, c.site_width, c.site_gmin = (_dptr(k) for k in keep)
+    return c, keep
+
+
+def workspace_bytes(sc):
+    c, keep = make_config(sc)
+    return library().lbm_workspace_bytes(C.byref(c))
+
+
+class Lattice:
+    """One domain on the current GPU, advanced by the library's kernels."""
+
+    def __init__(self, sc, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the hybrid LB library needs a GPU")
+        L = library()
+        self.sc = sc
+        self.torch = torch
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.cfg, self._keep = make_config(sc)
+        self.dtype = np.float64 if self.cfg.precision == F64 else np.float32
+        nbytes = L.lbm_workspace_bytes(C.byref(self.cfg))
+        if nbytes == 0:
+            raise LbmError(-1, "lbm_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        rho0 = np.ascontiguousarray(sc["rho0"], dtype=np.float64)
+        T0 = np.ascontiguousarray(sc["T0"], dtype=np.float64)
+        nx, ny, nh = sc["nx"], sc["ny"], sc["heater_rows"]
+        if rho0.shape != (ny, nx) or T0.shape != (nh + ny, nx):
+            raise ValueError("initial field shapes do not match the lattice")
+        h = C.c_void_p()
+        rc = L.lbm_init(C.byref(self.cfg), C.c_void_p(self.ws.data_ptr()), nbytes,
+                        C.c_void_p(self.stream.cuda_stream), _dptr(rho0), _dptr(T0), C.byref(h))
+        if rc != 0:
+            raise LbmError(rc, "lbm_init")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            library().lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        rc = library().lbm_step(self.h, int(n))
+        if rc != 0:
+            raise LbmError(rc, "lbm_step")
+
+    def observe(self, check=True):
+        o = LbmObs()
+        rc = library().lbm_observe(self.h, C.byref(o))
+        d = {k: getattr(o, k) for k, _ in LbmObs._fields_}
+        d["status"] = rc
+        if check and rc != 0:
+            raise LbmError(rc, "lbm_observe")
+        return d
+
+    def _shape(self, name):
+        nx, ny, nh = self.sc["nx"], self.sc["ny"], self.sc["heater_rows"]
+        return {"f": (9, ny, nx), "T": (nh + ny, nx), "Gw": (nx,)}.get(name, (ny, nx))
+
+    def read(self, name):
+        """Host copy of a field, as float64."""
+        out = np.empty(self._shape(name), dtype=self.dtype)
+        rc = library().lbm_read_field(self.h, FIELDS[name], out.ctypes.data_as(C.c_void_p),
+                                      out.nbytes, 0)
+        if rc != 0:
+            raise LbmError(rc, "lbm_read_field")
+        return out.astype(np.float64)
+
+    def write(self, name, values):
+        arr = np.ascontiguousarray(np.asarray(values).reshape(self._shape(name)), dtype=self.dtype)
+        rc = library().lbm_write_field(self.h, FIELDS[name], arr.ctypes.data_as(C.c_void_p),
+                                       arr.nbytes, 0)
+        if rc != 0:
+            raise LbmError(rc, "lbm_write_field")

@@ -1,0 +1,86 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports every
+function include/lbm_api.h declares, and rejects bad configurations before touching
+the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1812_10375_amd import lbm, scenarios as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "lbm_api.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = lbm.library()
+    names = declared_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_struct_layout_matches_header():
+    # lbm_config: 2 uint32 + 9 int32/uint32 + 25 doubles + int32 + 3 pointers
+    assert C.sizeof(lbm.LbmConfig) == 8 + 36 + 4 + 25 * 8 + 8 + 24
+    assert C.sizeof(lbm.LbmObs) == 8 + 12 * 8 + 8 + 8
+
+
+def test_workspace_bytes_for_the_full_boiling_workload():
+    sc = S.pool_boiling(steps=1)
+    nb = lbm.workspace_bytes(sc)
+    nodes = 1024 * 1024
+    # two population copies, two T copies, rho/u, small extras
+    assert 2 * 9 * nodes * 4 < nb < 2 * 9 * nodes * 4 + 8 * 1049 * 1024 * 4 + (1 << 22)
+
+
+@pytest.mark.parametrize("change", [
+    {"nx": 0}, {"ny": 0}, {"n_sub": 0}, {"heater_rows": -1}, {"precision": "f16"},
+    {"ny": 1, "top_bc": "convective"}, {"G": 1.0}, {"tau_l": 0.5}, {"s_q": 2.0},
+    {"rho_v": 7.0}, {"k": 0.0}, {"g": float("nan")},
+])
+def test_invalid_configurations_are_rejected(change):
+    sc = S.film_evaporation(nx=16, ny=16, film=4)
+    sc.update(change)
+    if sc["precision"] not in ("f32", "f64"):
+        c, keep = lbm.make_config(dict(sc, precision="f32"))
+        c.precision = 7
+    else:
+        c, keep = lbm.make_config(sc)
+    assert lbm.library().lbm_workspace_bytes(C.byref(c)) == 0
+    h = C.c_void_p()
+    rho = np.zeros((1,))
+    fake = C.c_void_p(1 << 20)  # never dereferenced: the call fails before any device work
+    rc = lbm.library().lbm_init(C.byref(c), fake, 1 << 30, None, lbm._dptr(rho), lbm._dptr(rho), C.byref(h))
+    assert rc == -1
+
+
+def test_small_or_misaligned_workspace_is_rejected():
+    sc = S.film_evaporation(nx=16, ny=16, film=4)
+    c, keep = lbm.make_config(sc)
+    need = lbm.library().lbm_workspace_bytes(C.byref(c))
+    rho = np.ascontiguousarray(sc["rho0"])
+    T = np.ascontiguousarray(sc["T0"])
+    h = C.c_void_p()
+    L = lbm.library()
+    assert L.lbm_init(C.byref(c), C.c_void_p(1 << 20), need - 1, None, lbm._dptr(rho), lbm._dptr(T), C.byref(h)) == -2
+    assert L.lbm_init(C.byref(c), C.c_void_p((1 << 20) + 4), need, None, lbm._dptr(rho), lbm._dptr(T), C.byref(h)) == -1
+    assert L.lbm_step(None, 1) == -1
+    assert L.lbm_strerror(-2) == b"workspace too small"
+
+
+def test_product_package_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1812_10375_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle", text, re.M), fn
+                assert "liboracle" not in text and "lbm_oracle" not in text, fn

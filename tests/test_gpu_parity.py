@@ -1,0 +1,114 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the same
+seeded inputs.  FP64 runs must agree to 1e-12 relative; FP32 runs to
+max|drho|/rho_l <= 1e-4 over the pre-nucleation steps."""
+import numpy as np
+import pytest
+
+from paper_1812_10375_amd import scenarios as S
+from parity import errors, log, run_pair
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-4
+
+
+def _check64(sc, steps, tol=TOL64):
+    res, gpu, orc = run_pair(sc, steps)
+    e = errors(res)
+    log("[parity] errors %s" % {k: "%.2e" % v for k, v in e.items()})
+    assert e["rho"] < tol and e["T"] < tol and e["u"] < 1e3 * tol, e
+    og, oo = res["gpu_obs"], res["orc_obs"]
+    assert og["step"] == oo["step"] == steps
+    assert og["mass"] == pytest.approx(oo["mass"], rel=tol)
+    for k in ("dE_cum", "Q_bottom_cum", "Q_top_cum", "Q_surface_cum", "energy"):
+        assert og[k] == pytest.approx(oo[k], rel=1e-10, abs=1e-12 * max(1.0, abs(oo["Q_bottom_cum"]))), k
+    return res, e
+
+
+def test_fp64_interface_conduction_exact_energy():
+    # 8 x 256, walls at 0.87 Tc and 0.85 Tc, stagnant, no latent heat (Sec. 3.2 setting)
+    sc = S.interface_conduction(steps=1000)
+    res, e = _check64(sc, 1000)
+    og = res["gpu_obs"]
+    # the GPU conserves energy exactly too: stored change == heat through the walls
+    assert og["dE_cum"] == pytest.approx(og["Q_bottom_cum"] + og["Q_top_cum"], rel=1e-12)
+
+
+def test_fp64_interface_conduction_full_physics():
+    sc = S.interface_conduction(exact_energy=False, steps=1000)
+    _check64(sc, 1000)
+
+
+def test_fp64_ragged_pool_boiling():
+    # ragged in x (100 = 64 + 36) and in both T and fluid rows; heater, sites, gravity,
+    # convective outlet
+    sc = S.pool_boiling(nx=100, ny=70, heater_rows=5, n_sites=2, min_spacing=20, seed=5,
+                        precision="f64")
+    _check64(sc, 300)
+
+
+def test_fp64_film_constant_pressure_top():
+    sc = S.film_evaporation(nx=70, ny=50, film=12, superheat=0.05, seed=7, precision="f64")
+    _check64(sc, 300)
+
+
+@pytest.mark.parametrize("nx,ny,nh", [(1, 12, 0), (3, 2, 2), (65, 17, 1)])
+def test_fp64_degenerate_shapes(nx, ny, nh):
+    sc = S.pool_boiling(nx=nx, ny=ny, heater_rows=nh, n_sites=0, seed=1, precision="f64")
+    _check64(sc, 50)
+
+
+def test_fp64_energy_substeps_and_flux_bottom():
+    sc = S.film_evaporation(nx=40, ny=30, film=10, seed=3, precision="f64")
+    sc["n_sub"] = 3
+    sc["bottom_tbc"] = "flux"
+    sc["q_bottom"] = 2e-4
+    sc["heater_rows"] = 4
+    sc["T0"] = np.full((34, 40), S.T_SAT)
+    _check64(sc, 100)
+
+
+def test_fp64_isotropic_comparison_scheme():
+    sc = S.interface_conduction(nx=8, ny=64, steps=200)
+    sc["flags"] = ("freeze_eos_T", "no_advection", "no_latent", "diff_isotropic")
+    _check64(sc, 200)
+
+
+def test_zero_steps_leave_the_state():
+    from paper_1812_10375_amd.lbm import Lattice
+    sc = S.film_evaporation(nx=33, ny=20, film=6, precision="f64")
+    gpu = Lattice(sc)
+    gpu.step(0)
+    ob = gpu.observe()
+    assert ob["step"] == 0
+    assert gpu.read("T") == pytest.approx(sc["T0"], abs=0)
+    assert ob["mass"] == pytest.approx(sc["rho0"].sum(), rel=1e-14)
+
+
+def _check32(sc, steps):
+    res, gpu, orc = run_pair(sc, steps)
+    e = errors(res)
+    log("[parity] errors %s" % {k: "%.2e" % v for k, v in e.items()})
+    assert e["rho"] < TOL32, e
+    assert e["T"] < TOL32, e
+    og, oo = res["gpu_obs"], res["orc_obs"]
+    assert og["mass"] == pytest.approx(oo["mass"], rel=1e-6)
+    return res, e
+
+
+def test_fp32_film_evaporation_1000_steps():
+    sc = S.film_evaporation(steps=1000)     # 256 x 256, the film-evaporation workload
+    _check32(sc, 1000)
+
+
+def test_fp32_pool_boiling_cropped_1000_steps():
+    sc = S.pool_boiling(nx=256, ny=256, n_sites=2, min_spacing=64, seed=3)
+    _check32(sc, 1000)
+
+
+def test_fp32_pool_boiling_full_size_first_steps():
+    # the 1024 x 1024 + 25-row heater workload in the launch configuration the
+    # benchmark times, against the oracle over its first steps
+    sc = S.pool_boiling()
+    _check32(sc, 20)
