@@ -1,6 +1,13 @@
-"""Benchmark: throughput of the full hybrid LB step (collision-streaming + energy
-update + diagnostics) on the pool-boiling workload, 1024 x 1024 fluid nodes with a
-25-row conjugate heater, FP32 populations/temperature, FP64 EOS and reductions."""
+"""Benchmark: throughput of the full hybrid LB step (collision-streaming, energy update
+and FP64 diagnostics) on the pool-boiling workload -- 1024 x 1024 fluid nodes above a
+25-row conjugate heater, 8 nucleation sites, gravity, convective outlet -- with FP32
+populations and temperature and FP64 equation of state and reductions.
+
+Prints one JSON line: whole-step MLUPS (fluid-node updates per second), a roofline
+object for the dominant kernel (algorithmic bytes per launch over its average duration,
+measured live with HIP events on the library's stream), and the FP64 CPU oracle timed
+on a bounded sample of the same workload.
+"""
 import argparse
 import json
 import os
@@ -9,6 +16,35 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def algorithmic_bytes(sc, real_bytes=4):
+    """Bytes a launch must move at the least (see the kernel notes):
+    collide: read and write the 9 populations of every fluid node;
+    energy:  read and write the temperature of every heater and fluid node."""
+    nodes = sc["nx"] * sc["ny"]
+    tnodes = sc["nx"] * (sc["ny"] + sc["heater_rows"])
+    return {"collide": 2 * 9 * real_bytes * nodes, "energy": 2 * real_bytes * tnodes}
+
+
+def cpu_baseline(sc, budget_s=20.0):
+    """FP64 oracle on the same workload, for as many steps as fit in about budget_s."""
+    from oracle.lbm import OracleSim
+    orc = OracleSim(sc)
+    t0 = time.perf_counter()
+    orc.step(1)
+    t1 = time.perf_counter() - t0
+    n = max(1, min(200, int(budget_s / max(t1, 1e-6)) - 1))
+    t0 = time.perf_counter()
+    orc.step(n)
+    dt = time.perf_counter() - t0
+    nodes = sc["nx"] * sc["ny"]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "%d steps (after 1 untimed) of the same %dx%d+%d workload, FP64, %.1f s"
+                      % (n, sc["nx"], sc["ny"], sc["heater_rows"], dt)}
 
 
 def main():
@@ -19,14 +55,28 @@ def main():
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--ny", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes five times "
+                         "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the method runs on one domain per GPU and this "
-              "build has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU: a domain runs on one GPU and there is no multi-GPU "
+              "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if "RANK" in os.environ and os.environ["RANK"] != "0":
+        sys.exit(0)
 
-    import numpy as np
     import torch
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.calibrate_copy, "launches": 5}))
+        return
     from paper_1812_10375_amd import scenarios as S
     from paper_1812_10375_amd.lbm import Lattice
 
@@ -37,15 +87,27 @@ def main():
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        start.record(stream)
-        lat.step(args.steps)
-        stop.record(stream)
+    lat.set_kernel_timing(True)
+    lat.kernel_times()  # reset
+    start.record(stream)
+    lat.step(args.steps)
+    stop.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
+    kt = lat.kernel_times()
+    lat.set_kernel_timing(False)
     ob = lat.observe(check=False)
     nodes = sc["nx"] * sc["ny"]
     mlups = nodes * args.steps / (ms * 1e-3) / 1e6
+
+    ab = algorithmic_bytes(sc)
+    per = {k: (v[0] / v[1] if v[1] else float("nan")) for k, v in kt.items()}
+    dom = max(kt, key=lambda k: kt[k][0])
+    achieved = ab[dom] / (per[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": "k_" + dom,
+                "bytes_per_launch": ab[dom], "avg_launch_ms": per[dom]}
+    step_bytes = ab["collide"] + ab["energy"]
     out = {
         "metric": "MLUPS 1024^2 FP32 plain",
         "value": mlups,
@@ -59,11 +121,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": sc["name"], "nx": sc["nx"], "ny": sc["ny"],
-                   "heater_rows": sc["heater_rows"], "sites": int(len(sc["sites"])),
+        "config": {"workload": sc["name"] + "+%d_heater" % sc["heater_rows"], "nx": sc["nx"],
+                   "ny": sc["ny"], "heater_rows": sc["heater_rows"], "sites": int(len(sc["sites"])),
                    "superheat_Tc": 0.10, "g": sc["g"], "seed": sc["seed"]},
+        "roofline": roofline,
+        "kernels_ms": {k: per[k] for k in per},
+        "step_algorithmic_GBps": step_bytes / (ms / args.steps * 1e-3) / 1e9,
         "status": ob["status"],
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
     print(json.dumps(out))
 
 

@@ -162,6 +162,15 @@ int lbm_read_field(lbm_ctx *h, int field, void *dst, size_t bytes, int dst_is_de
 /* Overwrite the populations (LBM_FIELD_F, pre-collision) or the temperature. */
 int lbm_write_field(lbm_ctx *h, int field, const void *src, size_t bytes, int src_is_device);
 
+/* Per-kernel timing for measurement.  While enabled, lbm_step records HIP events on
+ * the context's stream around the collide kernel and around the energy kernel(s) of
+ * every step.  lbm_kernel_times synchronises the stream, returns the summed durations
+ * (milliseconds) and launch counts since timing was enabled or last read, and resets
+ * them.  Disabled by default; enabling it adds two event records per kernel launch. */
+int lbm_set_kernel_timing(lbm_ctx *h, int enable);
+int lbm_kernel_times(lbm_ctx *h, double *collide_ms, int64_t *collide_launches,
+                     double *energy_ms, int64_t *energy_launches);
+
 /* Release the host-side context (the workspace stays the caller's). */
 int lbm_destroy(lbm_ctx *h);
 

@@ -48,23 +48,25 @@ bool valid_config(const lbm_config* c) {
   return true;
 }
 
-void grids(const lbm_config* c, int* ntxL, int* ntyL, int* ntxE, int* ntyE) {
+void grids(const lbm_config* c, int* ntxL, int* ntyL, int* ntxE, int* ntyE, int* tyE) {
   const bool f64 = c->precision == LBM_F64;
   const int ty = f64 ? TY_F64 : TY_F32;
-  const int tx = (f64 ? W3_F64 : W3_F32) - 6, tye = H3_E - 6;
+  const int tx = f64 ? TXE_F64 : TXE_F32;
   const int nT = c->heater_rows + c->ny;
   *ntxL = (c->nx + 63) / 64;
   *ntyL = (c->ny + ty - 1) / ty;
   *ntxE = (c->nx + tx - 1) / tx;
-  *ntyE = (nT + tye - 1) / tye;
+  // fewest tile rows of height <= EH_MAX, then the smallest height that covers nT
+  *ntyE = (nT + EH_MAX - 1) / EH_MAX;
+  *tyE = (nT + *ntyE - 1) / *ntyE;
 }
 
 Layout layout(const lbm_config* c) {
   Layout L{};
   const size_t R = c->precision == LBM_F64 ? 8 : 4;
   const size_t nx = c->nx, ny = c->ny, nT = (size_t)c->heater_rows + ny;
-  int ntxL, ntyL, ntxE, ntyE;
-  grids(c, &ntxL, &ntyL, &ntxE, &ntyE);
+  int ntxL, ntyL, ntxE, ntyE, tyE;
+  grids(c, &ntxL, &ntyL, &ntxE, &ntyE, &tyE);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -80,8 +82,11 @@ Layout layout(const lbm_config* c) {
   L.uy = take(nx * ny * R);
   L.topin = take(3 * nx * R);
   L.gw = take(nx * R);
-  L.partL = take((size_t)ntxL * ntyL * 2 * sizeof(double));
-  L.partE = take((size_t)ntxE * ntyE * 5 * sizeof(double));
+  for (int k = 0; k < 2; ++k) L.partL[k] = take((size_t)ntxL * ntyL * 3 * sizeof(double));
+  for (int k = 0; k < 2; ++k) L.pmin[k] = take((size_t)ntxE * sizeof(double));
+  for (int k = 0; k < 2; ++k) L.mstate[k] = take(sizeof(double));
+  L.hist = take((size_t)HIST * ntxE * ntyE * 5 * sizeof(double));
+  L.steps = take((size_t)HIST * 5 * sizeof(double));
   L.diag = take(sizeof(DevDiag));
   L.total = off;
   return L;
@@ -114,7 +119,7 @@ KParams make_params(const lbm_config* c) {
   P.top_bc = c->top_bc;
   P.bottom_tbc = c->bottom_tbc;
   P.top_tbc = c->top_tbc;
-  grids(c, &P.ntxL, &P.ntyL, &P.ntxE, &P.ntyE);
+  grids(c, &P.ntxL, &P.ntyL, &P.ntxE, &P.ntyE, &P.tyE);
   P.nblkL = P.ntxL * P.ntyL;
   P.nblkE = P.ntxE * P.ntyE;
   P.tyL = c->precision == LBM_F64 ? TY_F64 : TY_F32;
@@ -156,6 +161,7 @@ KParams make_params(const lbm_config* c) {
   P.s_e_raw = c->s_e;
   P.s_z_raw = c->s_zeta;
   P.rcw = c->rho_w * c->cv_w;
+  P.inv_rcw = P.rcw > 0 ? 1.0 / P.rcw : 0.0;
   P.lambda_w = c->lambda_w;
   P.T_bottom = c->T_bottom;
   P.T_top = c->T_top;
@@ -166,6 +172,27 @@ KParams make_params(const lbm_config* c) {
 int hip_ok(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 
 }  // namespace
+
+namespace lbmh {
+int timing_begin(lbm_ctx* h, int kind) {
+  if (!h->timing) return -1;
+  if (h->ev_used + 2 > h->ev_pool.size()) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -1;
+      h->ev_pool.push_back(e);
+    }
+  }
+  const int idx = (int)h->ev_used;
+  h->ev_used += 2;
+  h->ev_kind.push_back(kind);
+  (void)hipEventRecord(h->ev_pool[idx], h->stream);
+  return idx;
+}
+void timing_end(lbm_ctx* h, int idx) {
+  if (idx >= 0) (void)hipEventRecord(h->ev_pool[idx + 1], h->stream);
+}
+}  // namespace lbmh
 
 extern "C" {
 
@@ -195,6 +222,10 @@ int lbm_init(const lbm_config* cfg, void* d_workspace, size_t ws_bytes, void* hi
   h->tcur = 0;
   h->step = 0;
   h->bad = false;
+  h->timing = false;
+  h->ev_used = 0;
+  h->hist_first = 0;
+  h->hist_count = 0;
   const std::vector<double> gw = wall_profile(cfg);
   int rc = cfg->precision == LBM_F64 ? init_fields<double>(h, rho0_host, T0_host, gw.data())
                                      : init_fields<float>(h, rho0_host, T0_host, gw.data());
@@ -305,8 +336,36 @@ int lbm_write_field(lbm_ctx* h, int field, const void* src, size_t bytes, int sr
   return LBM_EINVAL;
 }
 
+int lbm_set_kernel_timing(lbm_ctx* h, int enable) {
+  if (!h) return LBM_EINVAL;
+  h->timing = enable != 0;
+  return LBM_OK;
+}
+
+int lbm_kernel_times(lbm_ctx* h, double* collide_ms, int64_t* collide_launches, double* energy_ms,
+                     int64_t* energy_launches) {
+  if (!h || !collide_ms || !collide_launches || !energy_ms || !energy_launches) return LBM_EINVAL;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return LBM_EHIP;
+  double t[2] = {0.0, 0.0};
+  int64_t n[2] = {0, 0};
+  for (size_t p = 0; p < h->ev_kind.size(); ++p) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev_pool[2 * p], h->ev_pool[2 * p + 1]) != hipSuccess) return LBM_EHIP;
+    t[h->ev_kind[p]] += ms;
+    n[h->ev_kind[p]] += 1;
+  }
+  h->ev_used = 0;
+  h->ev_kind.clear();
+  *collide_ms = t[0];
+  *collide_launches = n[0];
+  *energy_ms = t[1];
+  *energy_launches = n[1];
+  return LBM_OK;
+}
+
 int lbm_destroy(lbm_ctx* h) {
   if (!h) return LBM_EINVAL;
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
   return LBM_OK;
 }

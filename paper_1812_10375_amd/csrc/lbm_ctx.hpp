@@ -5,19 +5,24 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "lbm_api.h"
 #include "lbm_params.hpp"
 
 namespace lbmh {
 
-// Tiles.  k_collide: 64 columns x TY rows.  k_energy: (W3-6) x (H3-6) interior.
+// Tiles.  k_collide: 64 columns x TY rows, 256 threads.  k_energy: TX columns x
+// tyE rows (tyE <= lbmk::EH_MAX chosen per grid), 1024 threads.
 constexpr int TY_F32 = 16, TY_F64 = 8;
-constexpr int W3_F32 = 64, W3_F64 = 32, H3_E = 24;
+constexpr int TXE_F32 = 64, TXE_F64 = 32;
+constexpr int EH_MAX = 66;
+// Steps of energy partials kept before they are folded into the diagnostics.
+constexpr int HIST = 256;
 
 // Byte offsets of the arrays carved out of the caller's workspace.
 struct Layout {
-  size_t f[2], T[2], rho, ux, uy, topin, gw, partL, partE, diag, total;
+  size_t f[2], T[2], rho, ux, uy, topin, gw, partL[2], pmin[2], mstate[2], hist, steps, diag, total;
 };
 
 }  // namespace lbmh
@@ -31,6 +36,12 @@ struct lbm_ctx {
   int fcur, tcur;  // which population / temperature buffer holds the current state
   int64_t step;
   bool bad;
+  int hist_first, hist_count;  // history slots of the steps not yet folded in
+  // optional per-kernel timing: events recorded in pairs (start, stop) per launch
+  bool timing;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used;
+  std::vector<int> ev_kind;  // 0 collide, 1 energy, one entry per recorded pair
   template <typename T>
   T* at(size_t off) const {
     return reinterpret_cast<T*>(ws + off);
@@ -38,10 +49,14 @@ struct lbm_ctx {
 };
 
 namespace lbmh {
+// Event pair around one launch when timing is on: begin returns the start event's
+// index (or -1), end records the stop event.
+int timing_begin(lbm_ctx* h, int kind);
+void timing_end(lbm_ctx* h, int idx);
 // Per-precision launch code (T = float or double), defined in lbm_launch.hpp.
 template <typename T> void step_once(lbm_ctx* h);
 template <typename T> int scatter_state(lbm_ctx* h, const T* src, int src_is_rho);
-template <typename T> void finish_reductions(lbm_ctx* h);
+template <typename T> void finish_reductions(lbm_ctx* h);  // fold all pending steps
 template <typename T> void gather_populations(lbm_ctx* h, T* out);
 template <typename T> int init_fields(lbm_ctx* h, const double* rho0, const double* T0,
                                       const double* gw);

@@ -10,17 +10,30 @@
 //   T[2]      nT x nx       temperature, nT = heater_rows + ny (double-buffered)
 //   rho,ux,uy ny x nx       density and Eq. 5 velocity of the last collision
 //   gw        nx            wall strength of each bottom wall column (Eq. 10)
-//   partL     nblkL x 2     per-block FP64 partials of the collide kernel
-//   partE     nblkE x 5     per-block FP64 partials of the energy kernel
-//   diag      DevDiag       FP64 diagnostics, reduced in a fixed order every step
+//   partL[2]  nblkL x 3     per-tile FP64 partials of the collide kernel (post-collision
+//                           mass, max |u|^2, sum of u_y on row ny-2),
+//                           double-buffered by step parity
+//   pmin[2]   ntxE          net mass entering through an open top in the last step,
+//                           per top energy tile (inflow 4, 7, 8 minus outflow 2, 5, 6)
+//   mstate[2] 1             mass of the state at the start of the step
+//   hist      HIST x nblkE x 5  per-step, per-tile FP64 energy partials
+//   steps     HIST x 5      per-step totals of hist
+//   diag      DevDiag       FP64 diagnostics
 //
 // Per step two kernels run: k_collide (moments, EOS, forces, MRT collision) and
 // k_energy (all four RK4 stages of the temperature equation on an LDS tile with a
-// four-cell halo).  Block 0 of each kernel also finishes the previous kernel's
-// reductions, so no extra launch and no atomics are needed for the diagnostics.
+// four-cell halo).  The mass for rho_ave (Eq. 9) follows from continuity: streaming and
+// bounce-back move populations and the collision conserves their sum, so only the open
+// top changes it; every collide block adds the previous step's net inflow (same values,
+// same order) to the stored mass.  The energy kernel's top tiles apply the outlet rule
+// to their own columns and record their net inflow; the energy
+// diagnostics are reduced in step order later by k_reduce_steps / k_finish.  No
+// atomics touch the diagnostics, so reruns are bitwise identical.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "lbm_params.hpp"
 
@@ -48,8 +61,12 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
   return k * q + (k < r ? k : r) + (b >> 3);
 }
 
+// 1/v: exact for FP64, the hardware reciprocal (1 ulp) for FP32
 template <typename real>
-__device__ __forceinline__ real rcp(real v) { return real(1) / v; }
+__device__ __forceinline__ real fast_rcp(real v) {
+  if constexpr (sizeof(real) == 8) return 1.0 / v;
+  else return __builtin_amdgcn_rcpf(v);
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -64,10 +81,9 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
-// Block-wide sums of K doubles in a fixed order (wave tree, then waves in order).
-// Result is valid in thread 0.  red must hold 4*K (<= 32) doubles.
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
+// Block-wide sums over NW waves of K doubles (K*NW <= 96 doubles of scratch).
+template <int K, int NW>
+__device__ __forceinline__ void block_sum_n(double (&v)[K], double* red) {
   int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
@@ -78,7 +94,11 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = ((red[k] + red[K + k]) + red[2 * K + k]) + red[3 * K + k];
+    for (int k = 0; k < K; ++k) {
+      double a = red[k];
+      for (int q = 1; q < NW; ++q) a += red[q * K + k];
+      v[k] = a;
+    }
   __syncthreads();
 }
 
@@ -167,7 +187,9 @@ __device__ __forceinline__ void scatter(real* __restrict__ fs, real* __restrict_
 // ---------------------------------------------------------------------------
 // Eq. 7 with Eq. 28, in FP64: psi = sqrt(2 (p - rho/3) / G).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double eos_psi(const KParams& P, double r, double TE, unsigned& err) {
+// Returns the radicand 2 (p - rho/3) / G (0 when it is not positive); the caller takes
+// the square root in its own precision.
+__device__ __forceinline__ double eos_psi2(const KParams& P, double r, double TE, unsigned& err) {
   double phi;
   if (P.flags & FREEZE_EOS_T) {
     phi = P.phi_sat;
@@ -187,7 +209,7 @@ __device__ __forceinline__ double eos_psi(const KParams& P, double r, double TE,
     err |= (isfinite(rad) ? ERR_RADICAND : ERR_NONFINITE);
     return 0.0;
   }
-  return sqrt(rad);
+  return rad;
 }
 
 // The same in the operation order of the plain definition (used by the FP64 build,
@@ -230,8 +252,9 @@ __device__ __forceinline__ void collide(real f[9], real rho, real Fx, real Fy, r
   // momentum, summed in the order of the moment matrix rows
   const real jx = ((((f[1] - f[3]) + f[5]) - f[6]) - f[7]) + f[8];
   const real jy = ((((f[2] - f[4]) + f[5]) + f[6]) - f[7]) - f[8];
-  const real ux = (jx + h * Fx) / rho;
-  const real uy = (jy + h * Fy) / rho;
+  const real irho = fast_rcp(rho);
+  const real ux = (jx + h * Fx) * irho;
+  const real uy = (jy + h * Fy) * irho;
   const real s14 = (f[1] + f[2]) + (f[3] + f[4]);
   const real s58 = (f[5] + f[6]) + (f[7] + f[8]);
   const real m1 = real(-4) * f[0] - s14 + real(2) * s58;
@@ -255,7 +278,7 @@ __device__ __forceinline__ void collide(real f[9], real rho, real Fx, real Fy, r
   // viscous rate from tau interpolated linearly in density
   real w = (rho - c.rho_v) * c.inv_drho;
   w = w < real(0) ? real(0) : (w > real(1) ? real(1) : w);
-  const real snu = real(1) / (c.tau_v + c.dtau * w);
+  const real snu = fast_rcp(c.tau_v + c.dtau * w);
   const real cnu = real(1) - h * snu;
   const real d1 = -c.s_e * (m1 - e1) + c.c_e * S1;
   const real d2 = -c.s_z * (m2 - e2) + c.c_z * S2;
@@ -369,105 +392,46 @@ __device__ __forceinline__ void collide_plain(const KParams& P, double f[9], dou
 // Reductions that finish one kernel's partials inside the next kernel's block 0.
 // ---------------------------------------------------------------------------
 
-// Mass (and max speed) of the collide kernel, plus the open-top inflow of the next
-// step, which is written here because it needs the whole row below the top.
-template <typename real>
-__device__ void finish_collide(const KParams& P, const double* __restrict__ partL,
-                               const real* __restrict__ fpost, real* __restrict__ topin,
-                               const real* __restrict__ uxa, const real* __restrict__ uya,
-                               DevDiag* __restrict__ diag, bool apply_top, double* red) {
-  const int t = threadIdx.x;
-  double v[2] = {0.0, 0.0};
-  for (int b = t; b < P.nblkL; b += NT) {
-    v[0] += partL[2 * b];
-    v[1] = fmax(v[1], partL[2 * b + 1]);
-  }
-  // max over the block through the same fixed tree (max is order-free anyway)
-  double vm = wave_max(v[1]);
-  double vs[2] = {v[0], 0.0};
-  __syncthreads();
-  if ((t & 63) == 0) red[8 + (t >> 6)] = vm;
-  block_sum<2>(vs, red);
-  double mass = vs[0];
-  double vmax = fmax(fmax(red[8], red[9]), fmax(red[10], red[11]));
-  __syncthreads();
-  if (apply_top && P.top_bc != TOP_WALL) {
-    const int nx = P.nx, ny = P.ny;
-    const size_t N = (size_t)nx * ny;
-    const size_t below = (size_t)(ny - 2) * nx, top = (size_t)(ny - 1) * nx;
-    double U = 0.0;
-    if (P.top_bc == TOP_CONVECTIVE) {
-      double us[1] = {0.0};
-      for (int x = t; x < nx; x += NT) us[0] += (double)uya[below + x];
-      block_sum<1>(us, red);
-      if (t == 0) red[12] = us[0];
-      __syncthreads();
-      U = red[12] / nx;
-      if (U < 0.0) U = 0.0;
-      __syncthreads();
-    }
-    double ms[1] = {0.0};
-    for (int x = t; x < nx; x += NT) {
-      real in4, in7, in8;
-      if (P.top_bc == TOP_CONST_PRESSURE) {
-        // equilibrium at rho_v with the velocity of the row below
-        const real r = (real)P.rho_v, ux = uxa[below + x], uy = uya[below + x];
-        const real usq = real(1.5) * (ux * ux + uy * uy);
-        const real w1 = r / real(9), w2 = r / real(36);
-        const real e4 = -uy, e7 = -ux - uy, e8 = ux - uy;
-        in4 = w1 * (real(1) + real(3) * e4 + real(4.5) * e4 * e4 - usq);
-        in7 = w2 * (real(1) + real(3) * e7 + real(4.5) * e7 * e7 - usq);
-        in8 = w2 * (real(1) + real(3) * e8 + real(4.5) * e8 * e8 - usq);
-      } else {
-        // convective outlet: (f^n(top) + U f^{n+1}(top-1)) / (1 + U), where the new
-        // populations of the row below are pulled from the top row's post-collision
-        const real Ur = (real)U, inv = real(1) / (real(1) + Ur);
-        const int xm = wrap1(x - 1, nx), xp = wrap1(x + 1, nx);
-        in4 = (topin[x] + Ur * fpost[4 * N + top + x]) * inv;
-        in7 = (topin[nx + x] + Ur * fpost[7 * N + top + xp]) * inv;
-        in8 = (topin[2 * nx + x] + Ur * fpost[8 * N + top + xm]) * inv;
-      }
-      topin[x] = in4;
-      topin[nx + x] = in7;
-      topin[2 * nx + x] = in8;
-      ms[0] += (double)in4 + (double)in7 + (double)in8;
-    }
-    block_sum<1>(ms, red);
-    mass += ms[0];
-  }
-  if (t == 0) {
-    diag->mass = mass;
-    diag->rho_ave = mass / ((double)P.nx * (double)P.ny);
-    diag->max_speed = sqrt(vmax);
-    diag->L_pending = 0;
-  }
-}
+// Scratch layout of `red` (at least RED_SIZE doubles): [0, 96) block sums,
+// [96, 112) per-wave maxima, [112] broadcast slot.
+constexpr int RED_SIZE = 128;
 
-// Energy, heat and Welford statistics of the energy kernel(s) of the last step.
-__device__ void finish_energy(const KParams& P, const double* __restrict__ partE,
-                              DevDiag* __restrict__ diag, double* red) {
-  const int t = threadIdx.x;
-  double v[5] = {0, 0, 0, 0, 0};
-  for (int b = t; b < P.nblkE; b += NT)
-#pragma unroll
-    for (int k = 0; k < 5; ++k) v[k] += partE[5 * b + k];
-  block_sum<5>(v, red);
-  if (t == 0) {
-    DevDiag& d = *diag;
-    d.dE_cum += v[0];
-    d.energy = v[1];
-    d.Q_bottom_cum += v[2];
-    d.Q_top_cum += v[3];
-    d.Q_surface_cum += v[4];
-    d.q_bottom = v[2] / P.nx;
-    d.q_surface = v[4] / P.nx;
-    d.nred += 1;
-    const double cnt = (double)d.nred, q = d.q_bottom;
-    const double dl = q - d.q_mean;
-    d.q_mean += dl / cnt;
-    d.q_m2 += dl * (q - d.q_mean);
-    d.e_pending = 0;
+// Populations 4, 7, 8 entering the top row at column x for the next step:
+//   constant pressure (Sec. 3.3): equilibrium at rho_v with the velocity of the row below;
+//   convective outlet (Sec. 4.2): (f^n(top) + U f^{n+1}(top-1)) / (1 + U), where the new
+//   populations of the row below are pulled from the top row's post-collision values.
+// Returns the net mass change of the column: inflow minus the outflow of 2, 5, 6.
+template <typename real>
+__device__ __forceinline__ double outlet_column(const KParams& P, int x, real U,
+                                                const real* __restrict__ fpost,
+                                                real* __restrict__ topin,
+                                                const real* __restrict__ uxa,
+                                                const real* __restrict__ uya) {
+  const int nx = P.nx, ny = P.ny;
+  const size_t N = (size_t)nx * ny;
+  const size_t below = (size_t)(ny - 2) * nx, top = (size_t)(ny - 1) * nx;
+  real in4, in7, in8;
+  if (P.top_bc == TOP_CONST_PRESSURE) {
+    const real r = (real)P.rho_v, ux = uxa[below + x], uy = uya[below + x];
+    const real usq = real(1.5) * (ux * ux + uy * uy);
+    const real w1 = r / real(9), w2 = r / real(36);
+    const real e4 = -uy, e7 = -ux - uy, e8 = ux - uy;
+    in4 = w1 * (real(1) + real(3) * e4 + real(4.5) * e4 * e4 - usq);
+    in7 = w2 * (real(1) + real(3) * e7 + real(4.5) * e7 * e7 - usq);
+    in8 = w2 * (real(1) + real(3) * e8 + real(4.5) * e8 * e8 - usq);
+  } else {
+    const real inv = real(1) / (real(1) + U);
+    const int xm = wrap1(x - 1, nx), xp = wrap1(x + 1, nx);
+    in4 = (topin[x] + U * fpost[4 * N + top + x]) * inv;
+    in7 = (topin[nx + x] + U * fpost[7 * N + top + xp]) * inv;
+    in8 = (topin[2 * nx + x] + U * fpost[8 * N + top + xm]) * inv;
   }
+  topin[x] = in4;
+  topin[nx + x] = in7;
+  topin[2 * nx + x] = in8;
+  // populations 2, 5, 6 of the top row leave through the opening
+  const real out = (fpost[2 * N + top + x] + fpost[5 * N + top + x]) + fpost[6 * N + top + x];
+  return (((double)in4 + (double)in7) + (double)in8) - (double)out;
 }
 
 // ---------------------------------------------------------------------------
@@ -482,25 +446,26 @@ __global__ void __launch_bounds__(NT)
     k_collide(const KParams P, const real* __restrict__ fsrc, real* __restrict__ fdst,
               const real* __restrict__ topin, const real* __restrict__ Tcur,
               const real* __restrict__ gw, real* __restrict__ rho_out, real* __restrict__ ux_out,
-              real* __restrict__ uy_out, double* __restrict__ partL,
-              const double* __restrict__ partE, DevDiag* __restrict__ diag, long long step) {
+              real* __restrict__ uy_out, const double* __restrict__ mstate_prev,
+              const double* __restrict__ pmin_prev, double* __restrict__ mstate_cur,
+              double* __restrict__ partL_out, DevDiag* __restrict__ diag, long long step) {
   constexpr int RPT = TY / 4;  // rows per thread
   constexpr int LW = 66;
   __shared__ real spsi[TY + 2][LW];
-  __shared__ double red[32];
-  __shared__ double s_rho_ave;
+  __shared__ double red[RED_SIZE];
 
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
 
-  __shared__ int s_pending;
-  if (blockIdx.x == 0) {
-    if (t == 0) s_pending = diag->e_pending;
-    __syncthreads();
-    if (s_pending) finish_energy(P, partE, diag, red);
+  // Eq. 9: rho_ave = mass of the current state / fluid nodes, the mass being the stored
+  // mass of the previous state plus its net inflow through the top (thread 0 sums the
+  // same values in the same order in every block).
+  double mnow = 0.0;
+  if (t == 0) {
+    mnow = mstate_prev[0];
+    for (int b = 0; b < P.ntxE; ++b) mnow += pmin_prev[b];
   }
-  if (t == 0) s_rho_ave = diag->rho_ave;
 
   const int tile = xcd_tile(blockIdx.x, P.nblkL);
   const int x0 = (tile % P.ntxL) * 64, y0 = (tile / P.ntxL) * TY;
@@ -521,7 +486,7 @@ __global__ void __launch_bounds__(NT)
       rr[k] = r;
       const double TE = (P.flags & FREEZE_EOS_T) ? P.T_sat : (double)Tcur[(size_t)(y + P.nh) * nx + gxo];
       if constexpr (sizeof(real) == 8) ps = eos_psi_plain(P, r, TE, err);
-      else ps = (real)eos_psi(P, (double)r, TE, err);
+      else ps = sqrtf((float)eos_psi2(P, (double)r, TE, err));
     }
     spsi[ly + 1][lane + 1] = ps;
   }
@@ -544,11 +509,16 @@ __global__ void __launch_bounds__(NT)
       const double TE = (P.flags & FREEZE_EOS_T) ? P.T_sat : (double)Tcur[(size_t)(y + P.nh) * nx + gx];
       unsigned e2 = 0;
       if constexpr (sizeof(real) == 8) ps = eos_psi_plain(P, r, TE, e2);
-      else ps = (real)eos_psi(P, (double)r, TE, e2);
+      else ps = sqrtf((float)eos_psi2(P, (double)r, TE, e2));
     }
     spsi[ly + 1][lx + 1] = ps;
   }
-  __syncthreads();
+  if (t == 0) {
+    red[112] = mnow;
+    if (blockIdx.x == 0) mstate_cur[0] = mnow;
+  }
+  __syncthreads();  // publishes spsi and the mass
+  const double rho_ave_d = red[112] / ((double)nx * (double)ny);
 
   CollideConst<real> cc;
   cc.s_e = (real)P.s_e; cc.s_z = (real)P.s_z; cc.s_q = (real)P.s_q;
@@ -558,9 +528,9 @@ __global__ void __launch_bounds__(NT)
   cc.tau_v = (real)P.tau_v; cc.dtau = (real)P.dtau;
   const real w1 = real(1) / real(3), w2 = real(1) / real(12);
   const real a1 = w1 / real(3), a2 = w2 / real(3);  // Eq. 10 weights
-  const real negG = (real)(-P.G), gg = (real)P.g, rho_ave = (real)s_rho_ave;
+  const real negG = (real)(-P.G), gg = (real)P.g, rho_ave = (real)rho_ave_d;
   const bool open_top = P.top_bc != TOP_WALL;
-  double mass = 0.0;
+  double mass = 0.0, uyrow = 0.0;
   real umax2 = real(0);
 
 #pragma unroll
@@ -605,7 +575,7 @@ __global__ void __launch_bounds__(NT)
     if constexpr (sizeof(real) == 8) {
       collide_plain(P, f[k], Fx, Fy, fmx, fmy, pc, ux, uy);
     } else {
-      const real qsig = (fmx * fmx + fmy * fmy) / pc2;
+      const real qsig = (fmx * fmx + fmy * fmy) * fast_rcp(pc2);
       collide(f[k], r, Fx, Fy, qsig, cc, ux, uy);
     }
     const size_t n = (size_t)y * nx + gxo;
@@ -614,69 +584,69 @@ __global__ void __launch_bounds__(NT)
     rho_out[n] = r;
     ux_out[n] = ux;
     uy_out[n] = uy;
-    double ms = 0.0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) ms += (double)f[k][i];
-    if (y == ny - 1 && open_top) ms -= ((double)f[k][2] + (double)f[k][5]) + (double)f[k][6];
-    mass += ms;
+    // post-collision mass (per node in the field precision, accumulated in FP64); the
+    // open top's net exchange is added by the energy kernel's top tiles
+    const real ms = ((f[k][0] + f[k][1]) + (f[k][2] + f[k][3])) + ((f[k][4] + f[k][5]) + (f[k][6] + f[k][7])) + f[k][8];
+    mass += (double)ms;
     const real u2 = ux * ux + uy * uy;
     umax2 = u2 > umax2 ? u2 : umax2;
+    if (y == ny - 2) uyrow += (double)uy;
     if (!isfinite(u2)) err |= ERR_NONFINITE;
   }
   if (err) flag_error(diag, err, step);
-  double v[1] = {mass};
+  double v[2] = {mass, uyrow};
   double vm = wave_max((double)umax2);
   __syncthreads();
-  if (lane == 0) red[8 + wv] = vm;
-  block_sum<1>(v, red);
+  if (lane == 0) red[96 + wv] = vm;
+  block_sum_n<2, NT / 64>(v, red);
   if (t == 0) {
-    partL[2 * blockIdx.x] = v[0];
-    partL[2 * blockIdx.x + 1] = fmax(fmax(red[8], red[9]), fmax(red[10], red[11]));
-    if (blockIdx.x == 0) diag->L_pending = 1;  // read only by the next kernel
+    partL_out[3 * tile] = v[0];
+    partL_out[3 * tile + 1] = fmax(fmax(red[96], red[97]), fmax(red[98], red[99]));
+    partL_out[3 * tile + 2] = v[1];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Energy kernel: T^n -> T^{n+1} for a (W3-6) x (H3-6) tile of the temperature grid
-// (heater and fluid rows), rho^n and u^n frozen (Eq. 17-18, Eq. 22-27).
-// The tile, a four-cell halo and ghost rows sit in LDS; each of the four RK stages is
-// evaluated on a region one cell smaller than the previous one, so all stages run
-// with one read of T, rho, u and one write of T.  Thread t owns the cells t + 256k of
-// the stage-1 region (W3 x H3) and keeps their coefficients in registers.
+// Energy kernel: T^n -> T^{n+1} on a tile of the temperature grid (heater and fluid
+// rows), rho^n and u^n frozen (Eq. 17-18, Eq. 22-27).
+//
+// One 1024-thread workgroup holds a (TX+8) x (ty+8) tile in LDS: the tile, a
+// four-cell halo and the ghost rows (gfx950 gives a workgroup up to 160 KB of LDS).
+// Each RK stage is evaluated on a region one cell smaller than the previous one, so
+// all four stages run with one read of T, rho, u and one write of T.  Thread t owns
+// the cells t + 1024k of the stage-1 region and keeps their coefficients in
+// registers.  The tile height ty is chosen by the host (<= EH_MAX) so that the tiles
+// cover the grid in as few workgroups as possible.
 // ---------------------------------------------------------------------------
-template <typename real, int W3, int H3, bool ISO>
-__global__ void __launch_bounds__(NT)
+constexpr int ENT = 1024;   // threads per energy workgroup
+constexpr int EH_MAX = 66;  // largest interior tile height
+
+template <typename real, int TX, bool ISO>
+__global__ void __launch_bounds__(ENT)
     k_energy(const KParams P, const real* __restrict__ Tin, real* __restrict__ Tout,
              const real* __restrict__ rho, const real* __restrict__ uxa,
-             const real* __restrict__ uya, double* __restrict__ partE,
+             const real* __restrict__ uya, double* __restrict__ hist_slot,
              const real* __restrict__ fpost, real* __restrict__ topin,
-             const double* __restrict__ partL, DevDiag* __restrict__ diag, int sub, double dtd,
-             long long step) {
-  constexpr int W4 = W3 + 2, H4 = H3 + 2, NC = W3 * H3 / NT;
-  static_assert((W3 * H3) % NT == 0, "stage region must split evenly over the block");
-  constexpr int TX = W3 - 6, TYE = H3 - 6;
-  __shared__ real sA[H4][W4];
-  __shared__ real sB[H4][W4];
-  __shared__ real sFx[H4][W4];
-  __shared__ real sFy[H4][W4];
-  __shared__ real sUx[H4][W4];
-  __shared__ real sUy[H4][W4];
-  __shared__ double red[32];
+             const double* __restrict__ partL_cur, double* __restrict__ pmin_cur,
+             DevDiag* __restrict__ diag, int sub, double dtd, long long step) {
+  constexpr int W4 = TX + 8, W3 = TX + 6, H4M = EH_MAX + 8;
+  constexpr int NC = (W3 * (EH_MAX + 6) + ENT - 1) / ENT;  // stage-1 cells per thread
+  constexpr int NL = (W4 * H4M + ENT - 1) / ENT;           // load-phase cells per thread
+  __shared__ real sA[H4M][W4];   // stage values (T^n first)
+  __shared__ real sB[H4M][W4];   // lambda during set-up, then stage values
+  __shared__ real sFx[H4M][W4];  // u_x during set-up, then x-face conductivities
+  __shared__ real sFy[H4M][W4];  // u_y during set-up, then y-face conductivities
+  __shared__ double red[RED_SIZE];
 
   const int t = threadIdx.x;
   const int nx = P.nx, nT = P.nT, nh = P.nh;
-
-  __shared__ int s_pending;
-  if (blockIdx.x == 0 && sub == 0) {
-    if (t == 0) s_pending = diag->L_pending;
-    __syncthreads();
-    if (s_pending) finish_collide(P, partL, fpost, topin, uxa, uya, diag, true, red);
-  }
+  const int TY = P.tyE, H4 = TY + 8, H3 = TY + 6;
 
   const int tile = xcd_tile(blockIdx.x, P.nblkE);
-  const int x0 = (tile % P.ntxE) * TX, j0 = (tile / P.ntxE) * TYE;
-  const real cvk = (real)P.cvk;
+  const int x0 = (tile % P.ntxE) * TX, j0 = (tile / P.ntxE) * TY;
   const bool top_open = P.top_bc != TOP_WALL;
+  const bool fastwrap = nx >= W4;
+  const real cv = (real)P.cv, cvk = (real)P.cvk;
   // lambda = rho c_v k (Sec. 3.1)
   auto lam_of = [&](real r) -> real {
     if constexpr (sizeof(real) == 8) return r * P.cv * P.k;
@@ -685,45 +655,156 @@ __global__ void __launch_bounds__(NT)
   // Eq. 25 harmonic mean (dx = 1)
   auto face = [](real lp, real ln) -> real {
     if constexpr (sizeof(real) == 8) return 2.0 / (1.0 / lp + 1.0 / ln);
-    else return real(2) * lp * ln / (lp + ln);
+    else return real(2) * lp * ln * fast_rcp(lp + ln);
   };
 
-  // ---- load T, lambda (into sB), u over the tile + 4 halo + ghost rows ----
-  for (int c = t; c < W4 * H4; c += NT) {
-    const int lr = c / W4, lc = c - lr * W4;
-    const int j = j0 - 4 + lr;
-    const int gx = wrapm(x0 - 4 + lc, nx);
-    real T = real(0), lam = real(1), u = real(0), v = real(0);
-    if (j >= 0 && j < nT) {
-      T = Tin[(size_t)j * nx + gx];
-      if (j < nh) {
-        lam = (real)P.lambda_w;
-      } else {
-        const size_t n = (size_t)(j - nh) * nx + gx;
-        lam = lam_of(rho[n]);
-        u = uxa[n];
-        v = uya[n];
+  // ---- load T, lambda, u over the tile + 4 halo + ghost rows ----
+  // (a thread issues all its global loads before its first LDS store)
+  {
+    real lT[NL], lR[NL], lU[NL], lV[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int c = t + ENT * k;
+      lT[k] = real(0); lR[k] = real(-1); lU[k] = real(0); lV[k] = real(0);
+      if (c < W4 * H4) {
+        const int lr = c / W4, lc = c - lr * W4;
+        const int j = j0 - 4 + lr;
+        int gx = x0 - 4 + lc;
+        gx = fastwrap ? (gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx)) : wrapm(gx, nx);
+        if (j >= 0 && j < nT) {
+          lT[k] = Tin[(size_t)j * nx + gx];
+          if (j >= nh) {
+            const size_t n = (size_t)(j - nh) * nx + gx;
+            lR[k] = rho[n];
+            lU[k] = uxa[n];
+            lV[k] = uya[n];
+          }
+        } else if (j == -1) {
+          if (nh == 0) lR[k] = rho[gx];
+          if (P.bottom_tbc == TBC_FLUX) lT[k] = Tin[gx];
+        } else if (j == nT) {
+          const size_t n = (size_t)(P.ny - 1) * nx + gx;
+          lR[k] = rho[n];
+          if (P.top_tbc != TBC_DIRICHLET) lT[k] = Tin[(size_t)(nT - 1) * nx + gx];
+          if (top_open) { lU[k] = uxa[n]; lV[k] = uya[n]; }
+        }
       }
-    } else if (j == -1) {
-      lam = nh > 0 ? (real)P.lambda_w : lam_of(rho[gx]);
-      if (P.bottom_tbc == TBC_FLUX) T = Tin[gx] + (real)P.q_bottom / lam;
-      else T = (real)P.T_bottom;
-    } else if (j == nT) {
-      const size_t n = (size_t)(P.ny - 1) * nx + gx;
-      lam = lam_of(rho[n]);
-      if (P.top_tbc == TBC_DIRICHLET) T = (real)P.T_top;
-      else T = Tin[(size_t)(nT - 1) * nx + gx];
-      if (top_open) { u = uxa[n]; v = uya[n]; }
     }
-    sA[lr][lc] = T;
-    sB[lr][lc] = lam;
-    sUx[lr][lc] = u;
-    sUy[lr][lc] = v;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int c = t + ENT * k;
+      if (c < W4 * H4) {
+        const int lr = c / W4, lc = c - lr * W4;
+        const int j = j0 - 4 + lr;
+        // heater rows (and the ghost row below a heater) have lR < 0: lambda_w
+        real lam = lR[k] >= real(0) ? lam_of(lR[k]) : (real)P.lambda_w;
+        real T = lT[k];
+        if (j == -1) T = (P.bottom_tbc == TBC_FLUX) ? T + (real)P.q_bottom / lam : (real)P.T_bottom;
+        else if (j == nT && P.top_tbc == TBC_DIRICHLET) T = (real)P.T_top;
+        if (j < -1 || j > nT) lam = real(1);
+        sA[lr][lc] = T;
+        sB[lr][lc] = lam;
+        sFx[lr][lc] = lU[k];
+        sFy[lr][lc] = lV[k];
+      }
+    }
   }
   __syncthreads();
 
+  // ---- per-cell coefficients of the stage-1 cells this thread owns ----
+  real T0[NC], Cc[NC], cux[NC], cuy[NC], cla[NC], clb[NC], acc[NC];
+  real lamP[ISO ? NC : 1], glx[ISO ? NC : 1], gly[ISO ? NC : 1];
+  real crho[sizeof(real) == 8 ? NC : 1], cdv[sizeof(real) == 8 ? NC : 1];  // plain-order latent term
+  // heat capacity rho c_v per cell: FP64 in the FP64 build, FP32 otherwise
+  using rc_t = typename std::conditional<sizeof(real) == 8, double, float>::type;
+  rc_t rcv[NC];
+  // bit0 real node, bit1 fluid, bit2 bottom row, bit3 top row, bit4 surface row,
+  // bit5 output cell, bits 8..11 stage s is evaluated here
+  unsigned kind[NC];
+  int off[NC];  // LDS offset lr * W4 + lc
+  const real inv3 = real(1) / real(3), inv12 = real(1) / real(12);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int cell = t + ENT * k;
+    const int rr = cell / W3, cc = cell - rr * W3;
+    const int lr = rr + 1, lc = cc + 1;
+    const int j = j0 - 3 + rr;
+    const int xg = x0 - 3 + cc;
+    unsigned kd = 0;
+    T0[k] = real(0); Cc[k] = real(0); cux[k] = real(0); cuy[k] = real(0);
+    cla[k] = real(0); clb[k] = real(0); acc[k] = real(0);
+    rcv[k] = 0;
+    off[k] = lr * W4 + lc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (rr >= q && rr < H3 - q && cc >= q && cc < W3 - q) kd |= 256u << q;
+    if (rr < H3) {
+      T0[k] = sA[lr][lc];
+      if constexpr (ISO) {
+        // lambda and its Eq. 19 gradient for Eq. 21 (ghost rows copy the inner lambda)
+        lamP[k] = sB[lr][lc];
+        glx[k] = (sB[lr][lc + 1] - sB[lr][lc - 1]) * inv3 +
+                 ((sB[lr + 1][lc + 1] - sB[lr - 1][lc - 1]) + (sB[lr - 1][lc + 1] - sB[lr + 1][lc - 1])) * inv12;
+        gly[k] = (sB[lr + 1][lc] - sB[lr - 1][lc]) * inv3 +
+                 ((sB[lr + 1][lc + 1] - sB[lr - 1][lc - 1]) + (sB[lr + 1][lc - 1] - sB[lr - 1][lc + 1])) * inv12;
+      }
+      if (j >= 0 && j < nT) {
+        kd |= 1u;
+        if (j == 0) kd |= 4u;
+        if (j == nT - 1) kd |= 8u;
+        if (nh > 0 && j == nh) kd |= 16u;
+        if (rr >= 3 && rr < H3 - 3 && cc >= 3 && cc < W3 - 3 && xg < nx) kd |= 32u;
+        if (j < nh) {
+          rcv[k] = (rc_t)P.rcw;
+          Cc[k] = (real)P.inv_rcw;
+        } else {
+          kd |= 2u;
+          real r;
+          if constexpr (sizeof(real) == 8) {
+            const int gx = fastwrap ? (xg < 0 ? xg + nx : (xg >= nx ? xg - nx : xg)) : wrapm(xg, nx);
+            r = rho[(size_t)(j - nh) * nx + gx];
+            crho[k] = r;
+          } else {
+            r = sB[lr][lc] * (real)(1.0 / P.cvk);
+          }
+          if constexpr (sizeof(real) == 8) rcv[k] = (double)r * P.cv;
+          else rcv[k] = r * cv;
+          Cc[k] = fast_rcp(r * cv);
+          cux[k] = sFx[lr][lc];
+          cuy[k] = sFy[lr][lc];
+          if (!(P.flags & NO_LATENT)) {
+            // div u by Eq. 19 (u = 0 on solids, zero-gradient above an open top)
+            real dudx, dvdy;
+            if constexpr (sizeof(real) == 8) {
+              dudx = (sFx[lr][lc + 1] - sFx[lr][lc - 1]) / 3.0 + (sFx[lr + 1][lc + 1] - sFx[lr - 1][lc - 1]) / 12.0 +
+                     (sFx[lr - 1][lc + 1] - sFx[lr + 1][lc - 1]) / 12.0;
+              dvdy = (sFy[lr + 1][lc] - sFy[lr - 1][lc]) / 3.0 + (sFy[lr + 1][lc + 1] - sFy[lr - 1][lc - 1]) / 12.0 +
+                     (sFy[lr + 1][lc - 1] - sFy[lr - 1][lc + 1]) / 12.0;
+              cdv[k] = dudx + dvdy;
+            } else {
+              dudx = (sFx[lr][lc + 1] - sFx[lr][lc - 1]) * inv3 +
+                     ((sFx[lr + 1][lc + 1] - sFx[lr - 1][lc - 1]) + (sFx[lr - 1][lc + 1] - sFx[lr + 1][lc - 1])) * inv12;
+              dvdy = (sFy[lr + 1][lc] - sFy[lr - 1][lc]) * inv3 +
+                     ((sFy[lr + 1][lc + 1] - sFy[lr - 1][lc - 1]) + (sFy[lr + 1][lc - 1] - sFy[lr - 1][lc + 1])) * inv12;
+              // (dp/dT)_v = A(rho) - B(rho) phi'(T) (Eq. 28): A = rho R/(1 - b rho),
+              // B = a rho^2/(1 + 2 b rho - b^2 rho^2); no cancellation here, FP32 suffices
+              const real br = (real)P.b * r;
+              const real Ad = r * (real)P.R * fast_rcp(real(1) - br);
+              const real Bd = (real)P.a * r * r * fast_rcp(real(1) + real(2) * br - br * br);
+              const real cd = Cc[k] * (dudx + dvdy);
+              cla[k] = cd * Ad;
+              clb[k] = cd * Bd * (real)P.kappa;
+            }
+          }
+        }
+      }
+    }
+    kind[k] = kd;
+  }
+  __syncthreads();  // u and lambda have been consumed
+
   // ---- face conductivities (Eq. 25); a ghost face takes the inner node's lambda ----
-  for (int c = t; c < W4 * H4; c += NT) {
+  for (int c = t; c < W4 * H4; c += ENT) {
     const int lr = c / W4, lc = c - lr * W4;
     const int j = j0 - 4 + lr;
     const real lp = sB[lr][lc];
@@ -738,175 +819,114 @@ __global__ void __launch_bounds__(NT)
     sFx[lr][lc] = fx;
     sFy[lr][lc] = fy;
   }
-
-  // ---- per-cell coefficients of the cells this thread owns ----
-  real T0[NC], Cc[NC], cux[NC], cuy[NC], cla[NC], clb[NC], acc[NC];
-  real lamP[ISO ? NC : 1], glx[ISO ? NC : 1], gly[ISO ? NC : 1];
-  real crho[sizeof(real) == 8 ? NC : 1], cdv[sizeof(real) == 8 ? NC : 1];  // plain-order latent term
-  double rcv[NC];
-  unsigned kind[NC];  // bit0 real node, bit1 fluid, bit2 bottom row, bit3 top row, bit4 surface row, bit5 output cell
-  const real inv3 = real(1) / real(3), inv12 = real(1) / real(12);
-#pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    const int cell = t + NT * k;
-    const int rr = cell / W3, cc = cell - rr * W3;
-    const int lr = rr + 1, lc = cc + 1;
-    const int j = j0 - 3 + rr;
-    const int xg = x0 - 3 + cc;
-    unsigned kd = 0;
-    T0[k] = sA[lr][lc];
-    Cc[k] = real(0); cux[k] = real(0); cuy[k] = real(0); cla[k] = real(0); clb[k] = real(0);
-    acc[k] = real(0);
-    rcv[k] = 0.0;
-    if constexpr (ISO) {
-      // lambda and its Eq. 19 gradient for Eq. 21 (ghost rows copy the inner lambda)
-      lamP[k] = sB[lr][lc];
-      glx[k] = (sB[lr][lc + 1] - sB[lr][lc - 1]) * inv3 +
-               ((sB[lr + 1][lc + 1] - sB[lr - 1][lc - 1]) + (sB[lr - 1][lc + 1] - sB[lr + 1][lc - 1])) * inv12;
-      gly[k] = (sB[lr + 1][lc] - sB[lr - 1][lc]) * inv3 +
-               ((sB[lr + 1][lc + 1] - sB[lr - 1][lc - 1]) + (sB[lr + 1][lc - 1] - sB[lr - 1][lc + 1])) * inv12;
-    }
-    if (j >= 0 && j < nT) {
-      kd |= 1u;
-      if (j == 0) kd |= 4u;
-      if (j == nT - 1) kd |= 8u;
-      if (nh > 0 && j == nh) kd |= 16u;
-      if (rr >= 3 && rr < H3 - 3 && cc >= 3 && cc < W3 - 3 && xg < nx) kd |= 32u;
-      if (j < nh) {
-        rcv[k] = P.rcw;
-        Cc[k] = (real)(1.0 / P.rcw);
-      } else {
-        kd |= 2u;
-        const int gx = wrapm(xg, nx);
-        const real r = rho[(size_t)(j - nh) * nx + gx];
-        if constexpr (sizeof(real) == 8) crho[k] = r;
-        rcv[k] = (double)r * P.cv;
-        Cc[k] = real(1) / (r * (real)P.cv);
-        cux[k] = sUx[lr][lc];
-        cuy[k] = sUy[lr][lc];
-        if (!(P.flags & NO_LATENT)) {
-          // div u by Eq. 19 (u = 0 on solids, zero-gradient above an open top)
-          real dudx, dvdy;
-          if constexpr (sizeof(real) == 8) {
-            dudx = (sUx[lr][lc + 1] - sUx[lr][lc - 1]) / 3.0 + (sUx[lr + 1][lc + 1] - sUx[lr - 1][lc - 1]) / 12.0 +
-                   (sUx[lr - 1][lc + 1] - sUx[lr + 1][lc - 1]) / 12.0;
-            dvdy = (sUy[lr + 1][lc] - sUy[lr - 1][lc]) / 3.0 + (sUy[lr + 1][lc + 1] - sUy[lr - 1][lc - 1]) / 12.0 +
-                   (sUy[lr + 1][lc - 1] - sUy[lr - 1][lc + 1]) / 12.0;
-          } else {
-            dudx = (sUx[lr][lc + 1] - sUx[lr][lc - 1]) * inv3 + (sUx[lr + 1][lc + 1] - sUx[lr - 1][lc - 1]) * inv12 +
-                   (sUx[lr - 1][lc + 1] - sUx[lr + 1][lc - 1]) * inv12;
-            dvdy = (sUy[lr + 1][lc] - sUy[lr - 1][lc]) * inv3 + (sUy[lr + 1][lc + 1] - sUy[lr - 1][lc - 1]) * inv12 +
-                   (sUy[lr + 1][lc - 1] - sUy[lr - 1][lc + 1]) * inv12;
-          }
-          const real divu = dudx + dvdy;
-          cdv[k] = divu;
-          // (dp/dT)_v = A(rho) - B(rho) phi'(T); A, B in FP64 (Eq. 28)
-          const double rd = (double)r, br = P.b * rd;
-          const double Ad = rd * P.R / (1.0 - br);
-          const double Bd = P.a * rd * rd / (1.0 + 2.0 * br - br * br);
-          const double cd = (double)Cc[k] * (double)divu;
-          cla[k] = (real)(cd * Ad);
-          clb[k] = (real)(cd * Bd * P.kappa);
-        }
-      }
-    }
-    kind[k] = kd;
-  }
   __syncthreads();  // faces ready; sB is free for stage values
 
   const real dt = (real)dtd;
   const real kap = (real)P.kappa, onek = real(1) + (real)P.kappa, invTc = (real)P.inv_Tc;
-  const real qb = (real)P.q_bottom;
+  const real qb = (real)P.q_bottom, Tbot = (real)P.T_bottom, Ttop = (real)P.T_top;
   const bool flux_bottom = P.bottom_tbc == TBC_FLUX;
+  const bool top_dirichlet = P.top_tbc == TBC_DIRICHLET;
   double Qb = 0.0, Qt = 0.0, Qs = 0.0;
   const int fl = P.flags;
+  // A plain tile's halo holds fluid rows only (no heater, no ghost rows): its stages
+  // need no boundary handling.
+  const bool plain_tile = (j0 - 4 >= nh) && (j0 + TY + 3 <= nT - 1);
 
+  auto run_stages = [&](auto plain_tag) {
+    constexpr bool PLAIN = decltype(plain_tag)::value;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    real(*in)[W4] = (s & 1) ? sB : sA;
-    real(*out)[W4] = (s & 1) ? sA : sB;
-    const double wgt = (s == 0 || s == 3) ? 1.0 : 2.0;
+    for (int s = 0; s < 4; ++s) {
+      const real* inb = (s & 1) ? &sB[0][0] : &sA[0][0];
+      real* outb = (s & 1) ? &sA[0][0] : &sB[0][0];
+      const real* fxb = &sFx[0][0];
+      const real* fyb = &sFy[0][0];
+      const real wgt = (s == 0 || s == 3) ? real(1) : real(2);
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const int cell = t + NT * k;
-      const int rr = cell / W3, cc = cell - rr * W3;
-      if (!(kind[k] & 1u)) continue;
-      if (rr < s || rr >= H3 - s || cc < s || cc >= W3 - s) continue;
-      const int lr = rr + 1, lc = cc + 1;
-      const real Tp = in[lr][lc];
-      const real E = in[lr][lc + 1], W = in[lr][lc - 1], Nn = in[lr + 1][lc], S = in[lr - 1][lc];
-      const real fe = sFx[lr][lc], fw = sFx[lr][lc - 1], fn = sFy[lr][lc], fs = sFy[lr - 1][lc];
-      real qs;
-      if ((kind[k] & 4u) && flux_bottom) qs = qb;
-      else qs = fs * (S - Tp);
-      const real qn = fn * (Nn - Tp);
-      const real NE = in[lr + 1][lc + 1], NW = in[lr + 1][lc - 1];
-      const real SE = in[lr - 1][lc + 1], SW = in[lr - 1][lc - 1];
-      real gx = real(0), gy = real(0);
-      if (ISO || !(fl & NO_ADVECTION)) {
-        // Eq. 19 isotropic gradient
-        if constexpr (sizeof(real) == 8) {
-          gx = (E - W) / 3.0 + (NE - SW) / 12.0 + (SE - NW) / 12.0;
-          gy = (Nn - S) / 3.0 + (NE - SW) / 12.0 + (NW - SE) / 12.0;
+      for (int k = 0; k < NC; ++k) {
+        if constexpr (PLAIN) {
+          if (!(kind[k] & (256u << s))) continue;
         } else {
-          gx = (E - W) * inv3 + ((NE - SW) + (SE - NW)) * inv12;
-          gy = (Nn - S) * inv3 + ((NE - SW) + (NW - SE)) * inv12;
+          if ((kind[k] & ((256u << s) | 1u)) != ((256u << s) | 1u)) continue;
         }
-      }
-      real D;
-      if constexpr (!ISO) {
-        // Eq. 22-26: heat through the four faces of the control volume (dx = 1)
-        D = ((fe * (E - Tp) + fw * (W - Tp)) + qn) + qs;
-      } else {
-        // Eq. 21 with Eq. 20: lambda Lap T + grad lambda . grad T (comparison scheme)
-        const real lap =
-            (((((((((NE + NW) + SE) + SW) + real(4) * E) + real(4) * W) + real(4) * Nn) + real(4) * S) -
-              real(20) * Tp)) /
-            real(6);
-        D = lamP[k] * lap + (glx[k] * gx + gly[k] * gy);
-      }
-      real h;
-      if constexpr (sizeof(real) == 8) h = D / (real)rcv[k];
-      else h = Cc[k] * D;
-      if (kind[k] & 2u) {
-        if (!(fl & NO_ADVECTION)) h += -(cux[k] * gx + cuy[k] * gy);
-        if (!(fl & NO_LATENT)) {
+        const int o = off[k];
+        const real Tp = inb[o];
+        const real E = inb[o + 1], W = inb[o - 1], Nn = inb[o + W4], S = inb[o - W4];
+        const real fe = fxb[o], fw = fxb[o - 1], fn = fyb[o], fs = fyb[o - W4];
+        real qs;
+        if (!PLAIN && (kind[k] & 4u) && flux_bottom) qs = qb;
+        else qs = fs * (S - Tp);
+        const real qn = fn * (Nn - Tp);
+        const real NE = inb[o + W4 + 1], NW = inb[o + W4 - 1];
+        const real SE = inb[o - W4 + 1], SW = inb[o - W4 - 1];
+        real gx = real(0), gy = real(0);
+        if (ISO || !(fl & NO_ADVECTION)) {
+          // Eq. 19 isotropic gradient
           if constexpr (sizeof(real) == 8) {
-            // -(T/(rho c_v)) (dp/dT)_v div u, Eq. 17 with Eq. 28, in plain order
-            const double r = crho[k], b = P.b;
-            const double s1 = 1.0 + P.kappa * (1.0 - sqrt(Tp / P.Tc));
-            const double dphi = -P.kappa * s1 / sqrt(Tp * P.Tc);
-            const double dpdT = r * P.R / (1.0 - b * r) - P.a * dphi * r * r / (1.0 + 2.0 * b * r - b * b * r * r);
-            h += -(Tp / (real)rcv[k]) * dpdT * cdv[k];
+            gx = (E - W) / 3.0 + (NE - SW) / 12.0 + (SE - NW) / 12.0;
+            gy = (Nn - S) / 3.0 + (NE - SW) / 12.0 + (NW - SE) / 12.0;
           } else {
-            // -(T/(rho c_v)) (dp/dT)_v div u with T phi'(T) = -kappa s (1 + kappa - kappa s)
-            const real sg = sqrt(Tp * invTc);
-            h += -(cla[k] * Tp + clb[k] * sg * (onek - kap * sg));
+            gx = (E - W) * inv3 + ((NE - SW) + (SE - NW)) * inv12;
+            gy = (Nn - S) * inv3 + ((NE - SW) + (NW - SE)) * inv12;
           }
         }
+        real D;
+        if constexpr (!ISO) {
+          // Eq. 22-26: heat through the four faces of the control volume (dx = 1)
+          D = ((fe * (E - Tp) + fw * (W - Tp)) + qn) + qs;
+        } else {
+          // Eq. 21 with Eq. 20: lambda Lap T + grad lambda . grad T (comparison scheme)
+          const real lap =
+              (((((((((NE + NW) + SE) + SW) + real(4) * E) + real(4) * W) + real(4) * Nn) + real(4) * S) -
+                real(20) * Tp)) /
+              real(6);
+          D = lamP[k] * lap + (glx[k] * gx + gly[k] * gy);
+        }
+        real h;
+        if constexpr (sizeof(real) == 8) h = D / rcv[k];
+        else h = Cc[k] * D;
+        if (PLAIN || (kind[k] & 2u)) {
+          if (!(fl & NO_ADVECTION)) h += -(cux[k] * gx + cuy[k] * gy);
+          if (!(fl & NO_LATENT)) {
+            if constexpr (sizeof(real) == 8) {
+              // -(T/(rho c_v)) (dp/dT)_v div u, Eq. 17 with Eq. 28, in plain order
+              const double r = crho[k], b = P.b;
+              const double s1 = 1.0 + P.kappa * (1.0 - sqrt(Tp / P.Tc));
+              const double dphi = -P.kappa * s1 / sqrt(Tp * P.Tc);
+              const double dpdT = r * P.R / (1.0 - b * r) - P.a * dphi * r * r / (1.0 + 2.0 * b * r - b * b * r * r);
+              h += -(Tp / rcv[k]) * dpdT * cdv[k];
+            } else {
+              // -(T/(rho c_v)) (dp/dT)_v div u with T phi'(T) = -kappa s (1 + kappa - kappa s)
+              const real sg = __builtin_amdgcn_sqrtf(Tp * invTc);
+              h += -(cla[k] * Tp + clb[k] * sg * (onek - kap * sg));
+            }
+          }
+        }
+        if constexpr (!PLAIN) {
+          if ((kind[k] & 32u) && (kind[k] & (4u | 8u | 16u))) {
+            if (kind[k] & 4u) Qb += (double)(wgt * qs);
+            if ((kind[k] & 8u) && top_dirichlet) Qt += (double)(wgt * qn);
+            if (kind[k] & 16u) Qs += (double)(wgt * qs);
+          }
+        }
+        if (s < 3) {
+          const real cs = (s == 2) ? dt : real(0.5) * dt;
+          const real Yn = T0[k] + cs * h;
+          outb[o] = Yn;
+          acc[k] = (s == 0) ? h : acc[k] + real(2) * h;
+          if constexpr (!PLAIN) {
+            // ghost rows follow the stage value of the row next to them
+            if (kind[k] & 4u) outb[o - W4] = flux_bottom ? Yn + qb / fs : Tbot;
+            if (kind[k] & 8u) outb[o + W4] = top_dirichlet ? Ttop : Yn;
+          }
+        } else {
+          acc[k] = T0[k] + (dt / real(6)) * (acc[k] + h);
+        }
       }
-      if (kind[k] & 32u) {
-        const double w = wgt;
-        if (kind[k] & 4u) Qb += w * (double)qs;
-        if ((kind[k] & 8u) && P.top_tbc == TBC_DIRICHLET) Qt += w * (double)qn;
-        if (kind[k] & 16u) Qs += w * (double)qs;
-      }
-      if (s < 3) {
-        const real cs = (s == 2) ? dt : real(0.5) * dt;
-        const real Yn = T0[k] + cs * h;
-        out[lr][lc] = Yn;
-        acc[k] = (s == 0) ? h : acc[k] + real(2) * h;
-        // ghost rows follow the stage value of the row next to them
-        if ((kind[k] & 4u) && flux_bottom) out[lr - 1][lc] = Yn + qb / sFy[lr - 1][lc];
-        if ((kind[k] & 8u) && P.top_tbc != TBC_DIRICHLET) out[lr + 1][lc] = Yn;
-        if ((kind[k] & 4u) && !flux_bottom) out[lr - 1][lc] = (real)P.T_bottom;
-        if ((kind[k] & 8u) && P.top_tbc == TBC_DIRICHLET) out[lr + 1][lc] = (real)P.T_top;
-      } else {
-        acc[k] = T0[k] + (dt / real(6)) * (acc[k] + h);
-      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
+  };
+  if (plain_tile) run_stages(std::true_type{});
+  else run_stages(std::false_type{});
 
   // ---- write T^{n+1}, FP64 partials ----
   unsigned err = 0;
@@ -914,14 +934,14 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     if (!(kind[k] & 32u)) continue;
-    const int cell = t + NT * k;
+    const int cell = t + ENT * k;
     const int rr = cell / W3, cc = cell - rr * W3;
     const int j = j0 - 3 + rr, gx = x0 - 3 + cc;
     const real Tn = acc[k];
     if (!isfinite(Tn)) err |= ERR_NONFINITE;
     Tout[(size_t)j * nx + gx] = Tn;
-    v[0] += rcv[k] * ((double)Tn - (double)T0[k]);
-    v[1] += rcv[k] * (double)Tn;
+    v[0] += (double)rcv[k] * ((double)Tn - (double)T0[k]);
+    v[1] += (double)rcv[k] * (double)Tn;
   }
   if (err) flag_error(diag, err, step);
   const double d6 = dtd / 6.0;
@@ -929,9 +949,9 @@ __global__ void __launch_bounds__(NT)
   v[3] = Qt * d6;
   v[4] = Qs * d6;
   if (nh == 0) v[4] = v[2];
-  block_sum<5>(v, red);
+  block_sum_n<5, ENT / 64>(v, red);
   if (t == 0) {
-    double* pe = partE + 5 * blockIdx.x;
+    double* pe = hist_slot + 5 * tile;
     if (sub == 0) {
 #pragma unroll
       for (int k = 0; k < 5; ++k) pe[k] = v[k];
@@ -942,7 +962,26 @@ __global__ void __launch_bounds__(NT)
       pe[3] += v[3];
       pe[4] += v[4];
     }
-    if (blockIdx.x == 0) diag->e_pending = 1;  // read only by the next kernel
+  }
+  // Tiles holding the top fluid row set the open-top inflow of the next step for
+  // their own columns (once per LB step).
+  if (sub == 0 && j0 <= nT - 1 && nT - 1 < j0 + TY) {
+    double ms[1] = {0.0};
+    if (top_open) {
+      real U = real(0);
+      if (P.top_bc == TOP_CONVECTIVE) {
+        // mean outflow velocity of the row below the top, from the collide partials
+        const int ry = (P.ny - 2) / P.tyL;
+        double us = 0.0;
+        for (int bx = 0; bx < P.ntxL; ++bx) us += partL_cur[3 * (ry * P.ntxL + bx) + 2];
+        us /= nx;
+        U = (real)(us > 0.0 ? us : 0.0);
+      }
+      const int x = x0 + t;
+      if (t < TX && x < nx) ms[0] = outlet_column(P, x, U, fpost, topin, uxa, uya);
+    }
+    block_sum_n<1, ENT / 64>(ms, red);
+    if (t == 0) pmin_cur[tile % P.ntxE] = ms[0];
   }
 }
 
@@ -952,8 +991,8 @@ __global__ void __launch_bounds__(NT)
 template <typename real>
 __global__ void __launch_bounds__(NT)
     k_scatter(const KParams P, const real* __restrict__ src, int src_is_rho, real* __restrict__ fdst,
-              real* __restrict__ topin, double* __restrict__ partL, DevDiag* __restrict__ diag) {
-  __shared__ double red[32];
+              real* __restrict__ topin, double* __restrict__ partL_out) {
+  __shared__ double red[RED_SIZE];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
@@ -981,11 +1020,11 @@ __global__ void __launch_bounds__(NT)
     mass += ms;
   }
   double vv[1] = {mass};
-  block_sum<1>(vv, red);
+  block_sum_n<1, NT / 64>(vv, red);
   if (t == 0) {
-    partL[2 * blockIdx.x] = vv[0];
-    partL[2 * blockIdx.x + 1] = 0.0;
-    if (blockIdx.x == 0) diag->L_pending = 1;
+    partL_out[3 * tile] = vv[0];
+    partL_out[3 * tile + 1] = 0.0;
+    partL_out[3 * tile + 2] = 0.0;
   }
 }
 
@@ -1003,21 +1042,70 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
+// Per-step totals of the energy partials: block b sums history slot (first + b) % hist
+// over the energy tiles in tile order.  (Templated on the field type only so that each
+// precision's translation unit has its own copy.)
 template <typename real>
 __global__ void __launch_bounds__(NT)
-    k_finish(const KParams P, const double* __restrict__ partL, const double* __restrict__ partE,
-             const real* __restrict__ fpost, real* __restrict__ topin, const real* __restrict__ uxa,
-             const real* __restrict__ uya, DevDiag* __restrict__ diag) {
-  __shared__ double red[32];
-  __shared__ int s_pl, s_pe;
-  if (threadIdx.x == 0) {
-    s_pl = diag->L_pending;
-    s_pe = diag->e_pending;
+    k_reduce_steps(const KParams P, const double* __restrict__ hist, double* __restrict__ steps,
+                   int first, int hist_cap) {
+  __shared__ double red[RED_SIZE];
+  const int slot = (first + blockIdx.x) % hist_cap;
+  const double* h = hist + (size_t)slot * P.nblkE * 5;
+  double v[5] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < P.nblkE; b += NT)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] += h[5 * b + k];
+  block_sum_n<5, NT / 64>(v, red);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) steps[5 * slot + k] = v[k];
+}
+
+// Fold `count` reduced steps into the cumulative diagnostics in step order (running
+// mean / variance of the bottom heat flux by Welford's update), then the mass, rho_ave
+// and max speed of the current state from the last collide partials.
+template <typename real>
+__global__ void __launch_bounds__(NT)
+    k_finish(const KParams P, const double* __restrict__ steps, int first, int count, int hist_cap,
+             const double* __restrict__ partL_last, const double* __restrict__ pmin_last,
+             DevDiag* __restrict__ diag) {
+  __shared__ double red[RED_SIZE];
+  const int t = threadIdx.x;
+  if (t == 0) {
+    DevDiag& d = *diag;
+    for (int c = 0; c < count; ++c) {
+      const double* v = steps + 5 * ((first + c) % hist_cap);
+      d.dE_cum += v[0];
+      d.energy = v[1];
+      d.Q_bottom_cum += v[2];
+      d.Q_top_cum += v[3];
+      d.Q_surface_cum += v[4];
+      d.q_bottom = v[2] / P.nx;
+      d.q_surface = v[4] / P.nx;
+      d.nred += 1;
+      const double cnt = (double)d.nred, q = d.q_bottom;
+      const double dl = q - d.q_mean;
+      d.q_mean += dl / cnt;
+      d.q_m2 += dl * (q - d.q_mean);
+    }
   }
+  double mv[1] = {0.0};
+  double vm = 0.0;
+  for (int b = t; b < P.nblkL; b += NT) {
+    mv[0] += partL_last[3 * b];
+    vm = fmax(vm, partL_last[3 * b + 1]);
+  }
+  for (int b = t; b < P.ntxE; b += NT) mv[0] += pmin_last[b];
+  vm = wave_max(vm);
   __syncthreads();
-  if (s_pl) finish_collide(P, partL, fpost, topin, uxa, uya, diag, false, red);
-  __syncthreads();
-  if (s_pe) finish_energy(P, partE, diag, red);
+  if ((t & 63) == 0) red[96 + (t >> 6)] = vm;
+  block_sum_n<1, NT / 64>(mv, red);
+  if (t == 0) {
+    diag->mass = mv[0];
+    diag->rho_ave = mv[0] / ((double)P.nx * (double)P.ny);
+    diag->max_speed = sqrt(fmax(fmax(red[96], red[97]), fmax(red[98], red[99])));
+  }
 }
 
 template <typename real>

@@ -13,65 +13,89 @@ using lbmk::DevDiag;
 using lbmk::KParams;
 using lbmk::NT;
 
+// Fold every step of the history into the diagnostics (deterministic step order) and
+// recompute mass, rho_ave and max speed of the current state.
+template <typename real>
+void finish_reductions(lbm_ctx* h) {
+  const Layout& L = h->L;
+  const int last = (int)((h->step + 1) & 1);  // slot written by the last collide / scatter
+  if (h->hist_count > 0)
+    hipLaunchKernelGGL((lbmk::k_reduce_steps<real>), dim3(h->hist_count), dim3(NT), 0, h->stream, h->P,
+                       h->at<double>(L.hist), h->at<double>(L.steps), h->hist_first, HIST);
+  hipLaunchKernelGGL((lbmk::k_finish<real>), dim3(1), dim3(NT), 0, h->stream, h->P, h->at<double>(L.steps),
+                     h->hist_first, h->hist_count, HIST, h->at<double>(L.partL[last]),
+                     h->at<double>(L.pmin[last]), h->at<DevDiag>(L.diag));
+  h->hist_first = (h->hist_first + h->hist_count) % HIST;
+  h->hist_count = 0;
+}
+
 // One lattice step: k_collide, then k_energy once per energy sub-step (Eq. 27).
 template <typename real>
 void step_once(lbm_ctx* h) {
+  if (h->hist_count == HIST) finish_reductions<real>(h);
   const KParams& P = h->P;
   const Layout& L = h->L;
   constexpr bool f64 = sizeof(real) == 8;
+  const int cur = (int)(h->step & 1), prev = 1 - cur;
   real* fs = h->at<real>(L.f[h->fcur]);
   real* fd = h->at<real>(L.f[1 - h->fcur]);
   real* topin = h->at<real>(L.topin);
   real* rho = h->at<real>(L.rho);
   real* ux = h->at<real>(L.ux);
   real* uy = h->at<real>(L.uy);
-  double* partL = h->at<double>(L.partL);
-  double* partE = h->at<double>(L.partE);
   DevDiag* diag = h->at<DevDiag>(L.diag);
   const real* gw = h->at<real>(L.gw);
   const real* Tc = h->at<real>(L.T[h->tcur]);
+  int tev = timing_begin(h, 0);
   hipLaunchKernelGGL((lbmk::k_collide<real, f64 ? TY_F64 : TY_F32>), dim3(P.nblkL), dim3(NT), 0,
-                     h->stream, P, fs, fd, topin, Tc, gw, rho, ux, uy, partL, partE, diag,
-                     (long long)h->step);
+                     h->stream, P, fs, fd, topin, Tc, gw, rho, ux, uy, h->at<double>(L.mstate[prev]),
+                     h->at<double>(L.pmin[prev]), h->at<double>(L.mstate[cur]),
+                     h->at<double>(L.partL[cur]), diag, (long long)h->step);
+  timing_end(h, tev);
   const double dt = 1.0 / h->cfg.n_sub;
   const bool iso = (h->cfg.flags & LBM_DIFF_ISOTROPIC) != 0;
-  constexpr int W3 = f64 ? W3_F64 : W3_F32;
+  constexpr int TX = f64 ? TXE_F64 : TXE_F32;
+  static_assert(EH_MAX == lbmk::EH_MAX, "tile height bound shared with the kernel");
+  double* hslot = h->at<double>(L.hist) + (size_t)((h->hist_first + h->hist_count) % HIST) * P.nblkE * 5;
   for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
     const real* Tin = h->at<real>(L.T[h->tcur]);
     real* Tout = h->at<real>(L.T[1 - h->tcur]);
+    tev = timing_begin(h, 1);
     if (iso)
-      hipLaunchKernelGGL((lbmk::k_energy<real, W3, H3_E, true>), dim3(P.nblkE), dim3(NT), 0,
-                         h->stream, P, Tin, Tout, rho, ux, uy, partE, fd, topin, partL, diag, sub,
-                         dt, (long long)h->step);
+      hipLaunchKernelGGL((lbmk::k_energy<real, TX, true>), dim3(P.nblkE), dim3(lbmk::ENT), 0,
+                         h->stream, P, Tin, Tout, rho, ux, uy, hslot, fd, topin,
+                         h->at<double>(L.partL[cur]), h->at<double>(L.pmin[cur]), diag, sub, dt,
+                         (long long)h->step);
     else
-      hipLaunchKernelGGL((lbmk::k_energy<real, W3, H3_E, false>), dim3(P.nblkE), dim3(NT), 0,
-                         h->stream, P, Tin, Tout, rho, ux, uy, partE, fd, topin, partL, diag, sub,
-                         dt, (long long)h->step);
+      hipLaunchKernelGGL((lbmk::k_energy<real, TX, false>), dim3(P.nblkE), dim3(lbmk::ENT), 0,
+                         h->stream, P, Tin, Tout, rho, ux, uy, hslot, fd, topin,
+                         h->at<double>(L.partL[cur]), h->at<double>(L.pmin[cur]), diag, sub, dt,
+                         (long long)h->step);
+    timing_end(h, tev);
     h->tcur = 1 - h->tcur;
   }
+  h->hist_count += 1;
   h->fcur = 1 - h->fcur;
   h->step += 1;
 }
 
-// Finish any pending reductions (mass after a scatter, energy after a step).
-template <typename real>
-void finish_reductions(lbm_ctx* h) {
-  const Layout& L = h->L;
-  hipLaunchKernelGGL((lbmk::k_finish<real>), dim3(1), dim3(NT), 0, h->stream, h->P,
-                     h->at<double>(L.partL), h->at<double>(L.partE), h->at<real>(L.f[h->fcur]),
-                     h->at<real>(L.topin), h->at<real>(L.ux), h->at<real>(L.uy),
-                     h->at<DevDiag>(L.diag));
-}
-
 // Store pre-collision populations (or the equilibrium at rest of a density field)
-// as the current state, and reduce its mass.
+// as the current state; its mass partials go where the next collide kernel reads them.
 template <typename real>
 int scatter_state(lbm_ctx* h, const real* src, int src_is_rho) {
   const Layout& L = h->L;
+  const int last = (int)((h->step + 1) & 1);
+  if (hipMemsetAsync(h->at<double>(L.pmin[last]), 0, (size_t)h->P.ntxE * sizeof(double), h->stream) !=
+      hipSuccess)
+    return LBM_EHIP;
   hipLaunchKernelGGL((lbmk::k_scatter<real>), dim3(h->P.nblkL), dim3(NT), 0, h->stream, h->P, src,
                      src_is_rho, h->at<real>(L.f[h->fcur]), h->at<real>(L.topin),
-                     h->at<double>(L.partL), h->at<DevDiag>(L.diag));
+                     h->at<double>(L.partL[last]));
   finish_reductions<real>(h);
+  // the next collide kernel starts its mass bookkeeping from the summed mass
+  if (hipMemcpyAsync(h->at<double>(L.mstate[last]), &h->at<DevDiag>(L.diag)->mass, sizeof(double),
+                     hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+    return LBM_EHIP;
   return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EHIP;
 }
 

@@ -16,7 +16,7 @@ struct KParams {
   int nx, ny, nh, nT;
   int flags, top_bc, bottom_tbc, top_tbc;
   int ntxL, ntyL, nblkL, tyL;
-  int ntxE, ntyE, nblkE, pad0;
+  int ntxE, ntyE, nblkE, tyE;
   // equation of state (FP64)
   double a, b, R, G, Tc, inv_Tc, kappa, phi_sat, T_sat, inv3;
   // collision
@@ -24,15 +24,14 @@ struct KParams {
   double s_e, s_z, s_q, c_e, c_z, c_q, sig_e, sig_z;
   double g, Gw_top;
   // energy
-  double cv, k, cvk, rcw, lambda_w, T_bottom, T_top, q_bottom;
+  double cv, k, cvk, rcw, inv_rcw, lambda_w, T_bottom, T_top, q_bottom;
   double sigma, tau_l, s_e_raw, s_z_raw;
 };
 
 struct DevDiag {
   double mass, rho_ave, max_speed, energy, q_bottom, q_surface;
   double Q_bottom_cum, Q_top_cum, Q_surface_cum, dE_cum, q_mean, q_m2;
-  long long nred;
-  int L_pending, e_pending;
+  long long nred;  // steps folded into the running statistics
   unsigned int err;
   int pad;
   unsigned long long first_bad;

@@ -76,6 +76,11 @@ def library():
         L.lbm_write_field.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
         L.lbm_destroy.restype = C.c_int
         L.lbm_destroy.argtypes = [vp]
+        L.lbm_set_kernel_timing.restype = C.c_int
+        L.lbm_set_kernel_timing.argtypes = [vp, C.c_int]
+        L.lbm_kernel_times.restype = C.c_int
+        L.lbm_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.lbm_strerror.restype = C.c_char_p
         L.lbm_strerror.argtypes = [C.c_int]
         _lib = L
@@ -168,6 +173,20 @@ class Lattice:
         if check and rc != 0:
             raise LbmError(rc, "lbm_observe")
         return d
+
+    def set_kernel_timing(self, on):
+        rc = library().lbm_set_kernel_timing(self.h, int(bool(on)))
+        if rc != 0:
+            raise LbmError(rc, "lbm_set_kernel_timing")
+
+    def kernel_times(self):
+        """{'collide': (ms, launches), 'energy': (ms, launches)} since the last read."""
+        cm, em = C.c_double(), C.c_double()
+        cn, en = C.c_int64(), C.c_int64()
+        rc = library().lbm_kernel_times(self.h, C.byref(cm), C.byref(cn), C.byref(em), C.byref(en))
+        if rc != 0:
+            raise LbmError(rc, "lbm_kernel_times")
+        return {"collide": (cm.value, cn.value), "energy": (em.value, en.value)}
 
     def _shape(self, name):
         nx, ny, nh = self.sc["nx"], self.sc["ny"], self.sc["heater_rows"]

@@ -48,6 +48,13 @@ def test_fp64_ragged_pool_boiling():
     _check64(sc, 300)
 
 
+def test_fp64_tall_domain_with_interior_tiles():
+    # tall enough that some energy tiles have a halo without heater or ghost rows
+    sc = S.pool_boiling(nx=40, ny=200, heater_rows=5, n_sites=1, min_spacing=8, seed=9,
+                        precision="f64")
+    _check64(sc, 300)
+
+
 def test_fp64_film_constant_pressure_top():
     sc = S.film_evaporation(nx=70, ny=50, film=12, superheat=0.05, seed=7, precision="f64")
     _check64(sc, 300)
