@@ -149,8 +149,18 @@ size_t lbm_workspace_bytes(const lbm_config *cfg);
 int lbm_init(const lbm_config *cfg, void *d_workspace, size_t ws_bytes, void *hip_stream,
              const double *rho0_host, const double *T0_host, lbm_ctx **out);
 
-/* Enqueue nsteps (>= 0) complete steps on the context's stream; never synchronises. */
+/* Enqueue nsteps (>= 0) complete steps on the context's stream; never synchronises.
+ * Every kernel argument repeats with period 2 steps except the diagnostics history slot,
+ * which repeats every LBM_HISTORY_STEPS steps; a caller may therefore capture a multiple
+ * of LBM_HISTORY_STEPS steps (starting right after lbm_observe) into a HIP graph and
+ * replay it.  Device memory written: the workspace only; no memset or host copy is
+ * enqueued by lbm_step. */
+#define LBM_HISTORY_STEPS 256
 int lbm_step(lbm_ctx *h, int64_t nsteps);
+
+/* Use another stream from now on (for example a graph-capture stream).  The caller
+ * orders the switch against work already enqueued on the old stream. */
+int lbm_set_stream(lbm_ctx *h, void *hip_stream);
 
 /* Synchronise the stream and fill *out; LBM_ENONFINITE if the device flagged an error. */
 int lbm_observe(lbm_ctx *h, lbm_obs *out);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -48,25 +49,42 @@ bool valid_config(const lbm_config* c) {
   return true;
 }
 
-void grids(const lbm_config* c, int* ntxL, int* ntyL, int* ntxE, int* ntyE, int* tyE) {
+// Tile grids.  The collide tiles are fixed (64 x TY).  The energy tiles are as wide
+// as the 64-lane LDS rows allow (56 + 8 halo) and, for a device with `ncu` compute
+// units, as tall as possible while the tiles still fill every resident workgroup slot
+// in one round (at least E_HMIN rows unless the grid is shorter).  ncu = 0 gives the
+// largest tile count any device can use (for sizing the workspace).
+struct Grids {
+  int ntxL, ntyL, ntxE, ntyE, txE, tyE;
+};
+
+Grids grids(const lbm_config* c, int ncu) {
+  Grids g{};
   const bool f64 = c->precision == LBM_F64;
   const int ty = f64 ? TY_F64 : TY_F32;
-  const int tx = f64 ? TXE_F64 : TXE_F32;
   const int nT = c->heater_rows + c->ny;
-  *ntxL = (c->nx + 63) / 64;
-  *ntyL = (c->ny + ty - 1) / ty;
-  *ntxE = (c->nx + tx - 1) / tx;
-  // fewest tile rows of height <= EH_MAX, then the smallest height that covers nT
-  *ntyE = (nT + EH_MAX - 1) / EH_MAX;
-  *tyE = (nT + *ntyE - 1) / *ntyE;
+  g.ntxL = (c->nx + 63) / 64;
+  g.ntyL = (c->ny + ty - 1) / ty;
+  g.ntxE = (c->nx + E_TXMAX - 1) / E_TXMAX;
+  g.txE = (c->nx + g.ntxE - 1) / g.ntxE;
+  const int rows_min = (nT + E_HMAX - 1) / E_HMAX;
+  const int rows_max = (nT + E_HMIN - 1) / E_HMIN;
+  int rows = rows_max;
+  if (ncu > 0) {
+    const int slots = ncu * (f64 ? E_PER_CU_F64 : E_PER_CU_F32);
+    rows = std::max(rows_min, std::min(rows_max, slots / g.ntxE));
+  }
+  g.tyE = (nT + rows - 1) / rows;
+  g.ntyE = (nT + g.tyE - 1) / g.tyE;
+  return g;
 }
 
 Layout layout(const lbm_config* c) {
   Layout L{};
   const size_t R = c->precision == LBM_F64 ? 8 : 4;
   const size_t nx = c->nx, ny = c->ny, nT = (size_t)c->heater_rows + ny;
-  int ntxL, ntyL, ntxE, ntyE, tyE;
-  grids(c, &ntxL, &ntyL, &ntxE, &ntyE, &tyE);
+  const Grids g = grids(c, 0);  // upper bound on the energy tile count
+  const int ntxL = g.ntxL, ntyL = g.ntyL, ntxE = g.ntxE, ntyE = g.ntyE;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -85,6 +103,7 @@ Layout layout(const lbm_config* c) {
   for (int k = 0; k < 2; ++k) L.partL[k] = take((size_t)ntxL * ntyL * 3 * sizeof(double));
   for (int k = 0; k < 2; ++k) L.pmin[k] = take((size_t)ntxE * sizeof(double));
   for (int k = 0; k < 2; ++k) L.mstate[k] = take(sizeof(double));
+  for (int k = 0; k < 2; ++k) L.dstep[k] = take(sizeof(long long));
   L.hist = take((size_t)HIST * ntxE * ntyE * 5 * sizeof(double));
   L.steps = take((size_t)HIST * 5 * sizeof(double));
   L.diag = take(sizeof(DevDiag));
@@ -109,7 +128,7 @@ std::vector<double> wall_profile(const lbm_config* c) {
   return gw;
 }
 
-KParams make_params(const lbm_config* c) {
+KParams make_params(const lbm_config* c, int ncu) {
   KParams P{};
   P.nx = c->nx;
   P.ny = c->ny;
@@ -119,7 +138,13 @@ KParams make_params(const lbm_config* c) {
   P.top_bc = c->top_bc;
   P.bottom_tbc = c->bottom_tbc;
   P.top_tbc = c->top_tbc;
-  grids(c, &P.ntxL, &P.ntyL, &P.ntxE, &P.ntyE, &P.tyE);
+  const Grids g = grids(c, ncu);
+  P.ntxL = g.ntxL;
+  P.ntyL = g.ntyL;
+  P.ntxE = g.ntxE;
+  P.ntyE = g.ntyE;
+  P.txE = g.txE;
+  P.tyE = g.tyE;
   P.nblkL = P.ntxL * P.ntyL;
   P.nblkE = P.ntxE * P.ntyE;
   P.tyL = c->precision == LBM_F64 ? TY_F64 : TY_F32;
@@ -214,7 +239,14 @@ int lbm_init(const lbm_config* cfg, void* d_workspace, size_t ws_bytes, void* hi
   h->cfg = *cfg;
   h->cfg.n_sites = 0;  // the site table is consumed here (wall profile); do not keep host pointers
   h->cfg.site_xc = h->cfg.site_width = h->cfg.site_gmin = nullptr;
-  h->P = make_params(cfg);
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    delete h;
+    return LBM_EHIP;
+  }
+  h->ncu = ncu;
+  h->P = make_params(cfg, ncu);
   h->L = L;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   h->ws = reinterpret_cast<char*>(d_workspace);
@@ -245,6 +277,12 @@ int lbm_step(lbm_ctx* h, int64_t nsteps) {
     else step_once<float>(h);
   }
   return hip_ok(hipGetLastError());
+}
+
+int lbm_set_stream(lbm_ctx* h, void* hip_stream) {
+  if (!h) return LBM_EINVAL;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return LBM_OK;
 }
 
 int lbm_observe(lbm_ctx* h, lbm_obs* out) {

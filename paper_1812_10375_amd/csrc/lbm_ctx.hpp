@@ -12,17 +12,19 @@
 
 namespace lbmh {
 
-// Tiles.  k_collide: 64 columns x TY rows, 256 threads.  k_energy: TX columns x
-// tyE rows (tyE <= lbmk::EH_MAX chosen per grid), 1024 threads.
+// Tiles.  k_collide: 64 columns x TY rows, 256 threads.  k_energy: txE <= E_TXMAX
+// columns x tyE rows (E_HMIN <= tyE <= E_HMAX), E_NW waves; the sizes are chosen per
+// grid so that the tiles fill the CUs in one round when the grid allows it.
 constexpr int TY_F32 = 16, TY_F64 = 8;
-constexpr int TXE_F32 = 64, TXE_F64 = 32;
-constexpr int EH_MAX = 66;
+constexpr int E_NW = 8, E_HMAX = 48, E_HMIN = 8, E_TXMAX = 56;
+// energy workgroups resident per CU (LDS: 57 KB per FP32 workgroup, 115 KB per FP64)
+constexpr int E_PER_CU_F32 = 2, E_PER_CU_F64 = 1;
 // Steps of energy partials kept before they are folded into the diagnostics.
-constexpr int HIST = 256;
+constexpr int HIST = LBM_HISTORY_STEPS;
 
 // Byte offsets of the arrays carved out of the caller's workspace.
 struct Layout {
-  size_t f[2], T[2], rho, ux, uy, topin, gw, partL[2], pmin[2], mstate[2], hist, steps, diag, total;
+  size_t f[2], T[2], rho, ux, uy, topin, gw, partL[2], pmin[2], mstate[2], dstep[2], hist, steps, diag, total;
 };
 
 }  // namespace lbmh
@@ -37,6 +39,8 @@ struct lbm_ctx {
   int64_t step;
   bool bad;
   int hist_first, hist_count;  // history slots of the steps not yet folded in
+  int ncu;                     // compute units of the device
+  long long step_staging;      // host copy source for the device step counter
   // optional per-kernel timing: events recorded in pairs (start, stop) per launch
   bool timing;
   std::vector<hipEvent_t> ev_pool;

@@ -16,6 +16,9 @@
 //   pmin[2]   ntxE          net mass entering through an open top in the last step,
 //                           per top energy tile (inflow 4, 7, 8 minus outflow 2, 5, 6)
 //   mstate[2] 1             mass of the state at the start of the step
+//   dstep[2]  1             index of the step being computed (for error reports); the
+//                           collide kernel reads slot prev and writes slot cur, so no
+//                           kernel argument depends on the absolute step
 //   hist      HIST x nblkE x 5  per-step, per-tile FP64 energy partials
 //   steps     HIST x 5      per-step totals of hist
 //   diag      DevDiag       FP64 diagnostics
@@ -448,7 +451,8 @@ __global__ void __launch_bounds__(NT)
               const real* __restrict__ gw, real* __restrict__ rho_out, real* __restrict__ ux_out,
               real* __restrict__ uy_out, const double* __restrict__ mstate_prev,
               const double* __restrict__ pmin_prev, double* __restrict__ mstate_cur,
-              double* __restrict__ partL_out, DevDiag* __restrict__ diag, long long step) {
+              double* __restrict__ partL_out, DevDiag* __restrict__ diag,
+              const long long* __restrict__ dstep_prev, long long* __restrict__ dstep_cur) {
   constexpr int RPT = TY / 4;  // rows per thread
   constexpr int LW = 66;
   __shared__ real spsi[TY + 2][LW];
@@ -513,9 +517,13 @@ __global__ void __launch_bounds__(NT)
     }
     spsi[ly + 1][lx + 1] = ps;
   }
+  const long long step = dstep_prev[0];
   if (t == 0) {
     red[112] = mnow;
-    if (blockIdx.x == 0) mstate_cur[0] = mnow;
+    if (blockIdx.x == 0) {
+      mstate_cur[0] = mnow;
+      dstep_cur[0] = step + 1;
+    }
   }
   __syncthreads();  // publishes spsi and the mass
   const double rho_ave_d = red[112] / ((double)nx * (double)ny);
@@ -610,42 +618,42 @@ __global__ void __launch_bounds__(NT)
 // Energy kernel: T^n -> T^{n+1} on a tile of the temperature grid (heater and fluid
 // rows), rho^n and u^n frozen (Eq. 17-18, Eq. 22-27).
 //
-// One 1024-thread workgroup holds a (TX+8) x (ty+8) tile in LDS: the tile, a
-// four-cell halo and the ghost rows (gfx950 gives a workgroup up to 160 KB of LDS).
-// Each RK stage is evaluated on a region one cell smaller than the previous one, so
-// all four stages run with one read of T, rho, u and one write of T.  Thread t owns
-// the cells t + 1024k of the stage-1 region and keeps their coefficients in
-// registers.  The tile height ty is chosen by the host (<= EH_MAX) so that the tiles
-// cover the grid in as few workgroups as possible.
+// The tile (txE <= 56 columns by tyE rows, both chosen per grid) plus a four-cell halo
+// and the ghost rows sit in LDS as rows of 64 cells: lane = LDS column, and each wave
+// owns whole LDS rows, so everything that depends on the row (ghost, heater, fluid,
+// boundary, global address) is wave-uniform scalar work.  Each RK stage is evaluated
+// on a region one cell smaller than the previous one, so all four stages run with one
+// read of T, rho, u and one write of T.  LDS column c holds global column x0 - 4 + c
+// (periodic), LDS row r holds T row j0 - 4 + r.
 // ---------------------------------------------------------------------------
-constexpr int ENT = 1024;   // threads per energy workgroup
-constexpr int EH_MAX = 66;  // largest interior tile height
+constexpr int EW = 64;  // LDS row length = wavefront size
 
-template <typename real, int TX, bool ISO>
-__global__ void __launch_bounds__(ENT)
+template <typename real, bool ISO, int NW, int HMAX>
+__global__ void __launch_bounds__(NW * 64)
     k_energy(const KParams P, const real* __restrict__ Tin, real* __restrict__ Tout,
              const real* __restrict__ rho, const real* __restrict__ uxa,
              const real* __restrict__ uya, double* __restrict__ hist_slot,
              const real* __restrict__ fpost, real* __restrict__ topin,
              const double* __restrict__ partL_cur, double* __restrict__ pmin_cur,
-             DevDiag* __restrict__ diag, int sub, double dtd, long long step) {
-  constexpr int W4 = TX + 8, W3 = TX + 6, H4M = EH_MAX + 8;
-  constexpr int NC = (W3 * (EH_MAX + 6) + ENT - 1) / ENT;  // stage-1 cells per thread
-  constexpr int NL = (W4 * H4M + ENT - 1) / ENT;           // load-phase cells per thread
-  __shared__ real sA[H4M][W4];   // stage values (T^n first)
-  __shared__ real sB[H4M][W4];   // lambda during set-up, then stage values
-  __shared__ real sFx[H4M][W4];  // u_x during set-up, then x-face conductivities
-  __shared__ real sFy[H4M][W4];  // u_y during set-up, then y-face conductivities
+             DevDiag* __restrict__ diag, int sub, double dtd,
+             const long long* __restrict__ dstep_prev) {
+  constexpr int H4M = HMAX + 8;
+  constexpr int NR4 = (H4M + NW - 1) / NW;        // LDS rows per wave (load, faces)
+  constexpr int NC = (HMAX + 6 + NW - 1) / NW;    // stage-1 rows per wave
+  __shared__ real sA[H4M][EW];   // stage values (T^n first)
+  __shared__ real sB[H4M][EW];   // lambda during set-up, then stage values
+  __shared__ real sFx[H4M][EW];  // u_x during set-up, then x-face conductivities
+  __shared__ real sFy[H4M][EW];  // u_y during set-up, then y-face conductivities
   __shared__ double red[RED_SIZE];
 
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nx = P.nx, nT = P.nT, nh = P.nh;
-  const int TY = P.tyE, H4 = TY + 8, H3 = TY + 6;
-
+  const int TXr = P.txE, TY = P.tyE, H4 = TY + 8;
   const int tile = xcd_tile(blockIdx.x, P.nblkE);
-  const int x0 = (tile % P.ntxE) * TX, j0 = (tile / P.ntxE) * TY;
+  const int x0 = (tile % P.ntxE) * TXr, j0 = (tile / P.ntxE) * TY;
+  const int gx = wrapm(x0 - 4 + lane, nx);  // global column of this lane
   const bool top_open = P.top_bc != TOP_WALL;
-  const bool fastwrap = nx >= W4;
   const real cv = (real)P.cv, cvk = (real)P.cvk;
   // lambda = rho c_v k (Sec. 3.1)
   auto lam_of = [&](real r) -> real {
@@ -658,19 +666,14 @@ __global__ void __launch_bounds__(ENT)
     else return real(2) * lp * ln * fast_rcp(lp + ln);
   };
 
-  // ---- load T, lambda, u over the tile + 4 halo + ghost rows ----
-  // (a thread issues all its global loads before its first LDS store)
+  // ---- load T, lambda, u of the LDS rows this wave owns (loads first) ----
   {
-    real lT[NL], lR[NL], lU[NL], lV[NL];
+    real lT[NR4], lR[NR4], lU[NR4], lV[NR4];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-      const int c = t + ENT * k;
+    for (int k = 0; k < NR4; ++k) {
+      const int r = w + NW * k, j = j0 - 4 + r;
       lT[k] = real(0); lR[k] = real(-1); lU[k] = real(0); lV[k] = real(0);
-      if (c < W4 * H4) {
-        const int lr = c / W4, lc = c - lr * W4;
-        const int j = j0 - 4 + lr;
-        int gx = x0 - 4 + lc;
-        gx = fastwrap ? (gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx)) : wrapm(gx, nx);
+      if (r < H4) {
         if (j >= 0 && j < nT) {
           lT[k] = Tin[(size_t)j * nx + gx];
           if (j >= nh) {
@@ -691,106 +694,87 @@ __global__ void __launch_bounds__(ENT)
       }
     }
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-      const int c = t + ENT * k;
-      if (c < W4 * H4) {
-        const int lr = c / W4, lc = c - lr * W4;
-        const int j = j0 - 4 + lr;
+    for (int k = 0; k < NR4; ++k) {
+      const int r = w + NW * k, j = j0 - 4 + r;
+      if (r < H4) {
         // heater rows (and the ghost row below a heater) have lR < 0: lambda_w
         real lam = lR[k] >= real(0) ? lam_of(lR[k]) : (real)P.lambda_w;
         real T = lT[k];
         if (j == -1) T = (P.bottom_tbc == TBC_FLUX) ? T + (real)P.q_bottom / lam : (real)P.T_bottom;
         else if (j == nT && P.top_tbc == TBC_DIRICHLET) T = (real)P.T_top;
         if (j < -1 || j > nT) lam = real(1);
-        sA[lr][lc] = T;
-        sB[lr][lc] = lam;
-        sFx[lr][lc] = lU[k];
-        sFy[lr][lc] = lV[k];
+        sA[r][lane] = T;
+        sB[r][lane] = lam;
+        sFx[r][lane] = lU[k];
+        sFy[r][lane] = lV[k];
       }
     }
   }
   __syncthreads();
 
-  // ---- per-cell coefficients of the stage-1 cells this thread owns ----
+  // ---- per-cell coefficients of the stage-1 cells (LDS rows 1 + w + NW k, lanes 1..62) ----
   real T0[NC], Cc[NC], cux[NC], cuy[NC], cla[NC], clb[NC], acc[NC];
   real lamP[ISO ? NC : 1], glx[ISO ? NC : 1], gly[ISO ? NC : 1];
   real crho[sizeof(real) == 8 ? NC : 1], cdv[sizeof(real) == 8 ? NC : 1];  // plain-order latent term
-  // heat capacity rho c_v per cell: FP64 in the FP64 build, FP32 otherwise
   using rc_t = typename std::conditional<sizeof(real) == 8, double, float>::type;
   rc_t rcv[NC];
-  // bit0 real node, bit1 fluid, bit2 bottom row, bit3 top row, bit4 surface row,
-  // bit5 output cell, bits 8..11 stage s is evaluated here
-  unsigned kind[NC];
-  int off[NC];  // LDS offset lr * W4 + lc
   const real inv3 = real(1) / real(3), inv12 = real(1) / real(12);
+  const bool lane_r3 = lane >= 1 && lane <= EW - 2;
+  const bool lane_out = lane >= 4 && lane < 4 + TXr && x0 + lane - 4 < nx;
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
-    const int cell = t + ENT * k;
-    const int rr = cell / W3, cc = cell - rr * W3;
-    const int lr = rr + 1, lc = cc + 1;
-    const int j = j0 - 3 + rr;
-    const int xg = x0 - 3 + cc;
-    unsigned kd = 0;
+    const int r = 1 + w + NW * k, j = j0 - 4 + r;
     T0[k] = real(0); Cc[k] = real(0); cux[k] = real(0); cuy[k] = real(0);
     cla[k] = real(0); clb[k] = real(0); acc[k] = real(0);
     rcv[k] = 0;
-    off[k] = lr * W4 + lc;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (rr >= q && rr < H3 - q && cc >= q && cc < W3 - q) kd |= 256u << q;
-    if (rr < H3) {
-      T0[k] = sA[lr][lc];
+    if (r <= H4 - 2) {
+      T0[k] = sA[r][lane];
       if constexpr (ISO) {
         // lambda and its Eq. 19 gradient for Eq. 21 (ghost rows copy the inner lambda)
-        lamP[k] = sB[lr][lc];
-        glx[k] = (sB[lr][lc + 1] - sB[lr][lc - 1]) * inv3 +
-                 ((sB[lr + 1][lc + 1] - sB[lr - 1][lc - 1]) + (sB[lr - 1][lc + 1] - sB[lr + 1][lc - 1])) * inv12;
-        gly[k] = (sB[lr + 1][lc] - sB[lr - 1][lc]) * inv3 +
-                 ((sB[lr + 1][lc + 1] - sB[lr - 1][lc - 1]) + (sB[lr + 1][lc - 1] - sB[lr - 1][lc + 1])) * inv12;
+        if (lane_r3) {
+          lamP[k] = sB[r][lane];
+          glx[k] = (sB[r][lane + 1] - sB[r][lane - 1]) * inv3 +
+                   ((sB[r + 1][lane + 1] - sB[r - 1][lane - 1]) + (sB[r - 1][lane + 1] - sB[r + 1][lane - 1])) * inv12;
+          gly[k] = (sB[r + 1][lane] - sB[r - 1][lane]) * inv3 +
+                   ((sB[r + 1][lane + 1] - sB[r - 1][lane - 1]) + (sB[r + 1][lane - 1] - sB[r - 1][lane + 1])) * inv12;
+        }
       }
       if (j >= 0 && j < nT) {
-        kd |= 1u;
-        if (j == 0) kd |= 4u;
-        if (j == nT - 1) kd |= 8u;
-        if (nh > 0 && j == nh) kd |= 16u;
-        if (rr >= 3 && rr < H3 - 3 && cc >= 3 && cc < W3 - 3 && xg < nx) kd |= 32u;
         if (j < nh) {
           rcv[k] = (rc_t)P.rcw;
           Cc[k] = (real)P.inv_rcw;
         } else {
-          kd |= 2u;
-          real r;
+          real rr;
           if constexpr (sizeof(real) == 8) {
-            const int gx = fastwrap ? (xg < 0 ? xg + nx : (xg >= nx ? xg - nx : xg)) : wrapm(xg, nx);
-            r = rho[(size_t)(j - nh) * nx + gx];
-            crho[k] = r;
+            rr = rho[(size_t)(j - nh) * nx + gx];
+            crho[k] = rr;
+            rcv[k] = (double)rr * P.cv;
           } else {
-            r = sB[lr][lc] * (real)(1.0 / P.cvk);
+            rr = sB[r][lane] * (real)(1.0 / P.cvk);
+            rcv[k] = rr * cv;
           }
-          if constexpr (sizeof(real) == 8) rcv[k] = (double)r * P.cv;
-          else rcv[k] = r * cv;
-          Cc[k] = fast_rcp(r * cv);
-          cux[k] = sFx[lr][lc];
-          cuy[k] = sFy[lr][lc];
-          if (!(P.flags & NO_LATENT)) {
+          Cc[k] = fast_rcp(rr * cv);
+          cux[k] = sFx[r][lane];
+          cuy[k] = sFy[r][lane];
+          if (!(P.flags & NO_LATENT) && lane_r3) {
             // div u by Eq. 19 (u = 0 on solids, zero-gradient above an open top)
             real dudx, dvdy;
             if constexpr (sizeof(real) == 8) {
-              dudx = (sFx[lr][lc + 1] - sFx[lr][lc - 1]) / 3.0 + (sFx[lr + 1][lc + 1] - sFx[lr - 1][lc - 1]) / 12.0 +
-                     (sFx[lr - 1][lc + 1] - sFx[lr + 1][lc - 1]) / 12.0;
-              dvdy = (sFy[lr + 1][lc] - sFy[lr - 1][lc]) / 3.0 + (sFy[lr + 1][lc + 1] - sFy[lr - 1][lc - 1]) / 12.0 +
-                     (sFy[lr + 1][lc - 1] - sFy[lr - 1][lc + 1]) / 12.0;
+              dudx = (sFx[r][lane + 1] - sFx[r][lane - 1]) / 3.0 + (sFx[r + 1][lane + 1] - sFx[r - 1][lane - 1]) / 12.0 +
+                     (sFx[r - 1][lane + 1] - sFx[r + 1][lane - 1]) / 12.0;
+              dvdy = (sFy[r + 1][lane] - sFy[r - 1][lane]) / 3.0 + (sFy[r + 1][lane + 1] - sFy[r - 1][lane - 1]) / 12.0 +
+                     (sFy[r + 1][lane - 1] - sFy[r - 1][lane + 1]) / 12.0;
               cdv[k] = dudx + dvdy;
             } else {
-              dudx = (sFx[lr][lc + 1] - sFx[lr][lc - 1]) * inv3 +
-                     ((sFx[lr + 1][lc + 1] - sFx[lr - 1][lc - 1]) + (sFx[lr - 1][lc + 1] - sFx[lr + 1][lc - 1])) * inv12;
-              dvdy = (sFy[lr + 1][lc] - sFy[lr - 1][lc]) * inv3 +
-                     ((sFy[lr + 1][lc + 1] - sFy[lr - 1][lc - 1]) + (sFy[lr + 1][lc - 1] - sFy[lr - 1][lc + 1])) * inv12;
+              dudx = (sFx[r][lane + 1] - sFx[r][lane - 1]) * inv3 +
+                     ((sFx[r + 1][lane + 1] - sFx[r - 1][lane - 1]) + (sFx[r - 1][lane + 1] - sFx[r + 1][lane - 1])) * inv12;
+              dvdy = (sFy[r + 1][lane] - sFy[r - 1][lane]) * inv3 +
+                     ((sFy[r + 1][lane + 1] - sFy[r - 1][lane - 1]) + (sFy[r + 1][lane - 1] - sFy[r - 1][lane + 1])) * inv12;
               // (dp/dT)_v = A(rho) - B(rho) phi'(T) (Eq. 28): A = rho R/(1 - b rho),
               // B = a rho^2/(1 + 2 b rho - b^2 rho^2); no cancellation here, FP32 suffices
-              const real br = (real)P.b * r;
-              const real Ad = r * (real)P.R * fast_rcp(real(1) - br);
-              const real Bd = (real)P.a * r * r * fast_rcp(real(1) + real(2) * br - br * br);
+              const real br = (real)P.b * rr;
+              const real Ad = rr * (real)P.R * fast_rcp(real(1) - br);
+              const real Bd = (real)P.a * rr * rr * fast_rcp(real(1) + real(2) * br - br * br);
               const real cd = Cc[k] * (dudx + dvdy);
               cla[k] = cd * Ad;
               clb[k] = cd * Bd * (real)P.kappa;
@@ -799,25 +783,26 @@ __global__ void __launch_bounds__(ENT)
         }
       }
     }
-    kind[k] = kd;
   }
   __syncthreads();  // u and lambda have been consumed
 
   // ---- face conductivities (Eq. 25); a ghost face takes the inner node's lambda ----
-  for (int c = t; c < W4 * H4; c += ENT) {
-    const int lr = c / W4, lc = c - lr * W4;
-    const int j = j0 - 4 + lr;
-    const real lp = sB[lr][lc];
-    real fx = real(0), fy = real(0);
-    if (lc + 1 < W4) fx = face(lp, sB[lr][lc + 1]);
-    if (lr + 1 < H4) {
-      const real ln = sB[lr + 1][lc];
-      if (j == -1) fy = ln;
-      else if (j == nT - 1) fy = lp;
-      else fy = face(lp, ln);
+#pragma unroll
+  for (int k = 0; k < NR4; ++k) {
+    const int r = w + NW * k, j = j0 - 4 + r;
+    if (r < H4) {
+      const real lp = sB[r][lane];
+      real fx = real(0), fy = real(0);
+      if (lane + 1 < EW) fx = face(lp, sB[r][lane + 1]);
+      if (r + 1 < H4) {
+        const real ln = sB[r + 1][lane];
+        if (j == -1) fy = ln;
+        else if (j == nT - 1) fy = lp;
+        else fy = face(lp, ln);
+      }
+      sFx[r][lane] = fx;
+      sFy[r][lane] = fy;
     }
-    sFx[lr][lc] = fx;
-    sFy[lr][lc] = fy;
   }
   __syncthreads();  // faces ready; sB is free for stage values
 
@@ -841,32 +826,34 @@ __global__ void __launch_bounds__(ENT)
       const real* fxb = &sFx[0][0];
       const real* fyb = &sFy[0][0];
       const real wgt = (s == 0 || s == 3) ? real(1) : real(2);
+      const bool lane_s = lane >= 1 + s && lane < EW - 1 - s;
 #pragma unroll
       for (int k = 0; k < NC; ++k) {
-        if constexpr (PLAIN) {
-          if (!(kind[k] & (256u << s))) continue;
-        } else {
-          if ((kind[k] & ((256u << s) | 1u)) != ((256u << s) | 1u)) continue;
-        }
-        const int o = off[k];
+        const int r = 1 + w + NW * k, j = j0 - 4 + r;
+        // stage s covers LDS rows [1 + s, H4 - 1 - s) and lanes [1 + s, 63 - s)
+        if (r < 1 + s || r >= H4 - 1 - s) continue;
+        if (!PLAIN && (j < 0 || j >= nT)) continue;
+        if (!lane_s) continue;
+        const int o = r * EW + lane;
         const real Tp = inb[o];
-        const real E = inb[o + 1], W = inb[o - 1], Nn = inb[o + W4], S = inb[o - W4];
-        const real fe = fxb[o], fw = fxb[o - 1], fn = fyb[o], fs = fyb[o - W4];
+        const real E = inb[o + 1], W = inb[o - 1], Nn = inb[o + EW], S = inb[o - EW];
+        const real fe = fxb[o], fw = fxb[o - 1], fn = fyb[o], fs = fyb[o - EW];
+        const bool bottom = !PLAIN && j == 0, top = !PLAIN && j == nT - 1;
         real qs;
-        if (!PLAIN && (kind[k] & 4u) && flux_bottom) qs = qb;
+        if (bottom && flux_bottom) qs = qb;
         else qs = fs * (S - Tp);
         const real qn = fn * (Nn - Tp);
-        const real NE = inb[o + W4 + 1], NW = inb[o + W4 - 1];
-        const real SE = inb[o - W4 + 1], SW = inb[o - W4 - 1];
-        real gx = real(0), gy = real(0);
+        const real NE = inb[o + EW + 1], NW_ = inb[o + EW - 1];
+        const real SE = inb[o - EW + 1], SW = inb[o - EW - 1];
+        real gxd = real(0), gyd = real(0);
         if (ISO || !(fl & NO_ADVECTION)) {
           // Eq. 19 isotropic gradient
           if constexpr (sizeof(real) == 8) {
-            gx = (E - W) / 3.0 + (NE - SW) / 12.0 + (SE - NW) / 12.0;
-            gy = (Nn - S) / 3.0 + (NE - SW) / 12.0 + (NW - SE) / 12.0;
+            gxd = (E - W) / 3.0 + (NE - SW) / 12.0 + (SE - NW_) / 12.0;
+            gyd = (Nn - S) / 3.0 + (NE - SW) / 12.0 + (NW_ - SE) / 12.0;
           } else {
-            gx = (E - W) * inv3 + ((NE - SW) + (SE - NW)) * inv12;
-            gy = (Nn - S) * inv3 + ((NE - SW) + (NW - SE)) * inv12;
+            gxd = (E - W) * inv3 + ((NE - SW) + (SE - NW_)) * inv12;
+            gyd = (Nn - S) * inv3 + ((NE - SW) + (NW_ - SE)) * inv12;
           }
         }
         real D;
@@ -876,23 +863,23 @@ __global__ void __launch_bounds__(ENT)
         } else {
           // Eq. 21 with Eq. 20: lambda Lap T + grad lambda . grad T (comparison scheme)
           const real lap =
-              (((((((((NE + NW) + SE) + SW) + real(4) * E) + real(4) * W) + real(4) * Nn) + real(4) * S) -
+              (((((((((NE + NW_) + SE) + SW) + real(4) * E) + real(4) * W) + real(4) * Nn) + real(4) * S) -
                 real(20) * Tp)) /
               real(6);
-          D = lamP[k] * lap + (glx[k] * gx + gly[k] * gy);
+          D = lamP[k] * lap + (glx[k] * gxd + gly[k] * gyd);
         }
         real h;
         if constexpr (sizeof(real) == 8) h = D / rcv[k];
         else h = Cc[k] * D;
-        if (PLAIN || (kind[k] & 2u)) {
-          if (!(fl & NO_ADVECTION)) h += -(cux[k] * gx + cuy[k] * gy);
+        if (PLAIN || j >= nh) {
+          if (!(fl & NO_ADVECTION)) h += -(cux[k] * gxd + cuy[k] * gyd);
           if (!(fl & NO_LATENT)) {
             if constexpr (sizeof(real) == 8) {
               // -(T/(rho c_v)) (dp/dT)_v div u, Eq. 17 with Eq. 28, in plain order
-              const double r = crho[k], b = P.b;
+              const double rr = crho[k], b = P.b;
               const double s1 = 1.0 + P.kappa * (1.0 - sqrt(Tp / P.Tc));
               const double dphi = -P.kappa * s1 / sqrt(Tp * P.Tc);
-              const double dpdT = r * P.R / (1.0 - b * r) - P.a * dphi * r * r / (1.0 + 2.0 * b * r - b * b * r * r);
+              const double dpdT = rr * P.R / (1.0 - b * rr) - P.a * dphi * rr * rr / (1.0 + 2.0 * b * rr - b * b * rr * rr);
               h += -(Tp / rcv[k]) * dpdT * cdv[k];
             } else {
               // -(T/(rho c_v)) (dp/dT)_v div u with T phi'(T) = -kappa s (1 + kappa - kappa s)
@@ -902,10 +889,11 @@ __global__ void __launch_bounds__(ENT)
           }
         }
         if constexpr (!PLAIN) {
-          if ((kind[k] & 32u) && (kind[k] & (4u | 8u | 16u))) {
-            if (kind[k] & 4u) Qb += (double)(wgt * qs);
-            if ((kind[k] & 8u) && top_dirichlet) Qt += (double)(wgt * qn);
-            if (kind[k] & 16u) Qs += (double)(wgt * qs);
+          const bool out_row = r >= 4 && r < 4 + TY;
+          if (out_row && lane_out) {
+            if (bottom) Qb += (double)(wgt * qs);
+            if (top && top_dirichlet) Qt += (double)(wgt * qn);
+            if (nh > 0 && j == nh) Qs += (double)(wgt * qs);
           }
         }
         if (s < 3) {
@@ -915,8 +903,8 @@ __global__ void __launch_bounds__(ENT)
           acc[k] = (s == 0) ? h : acc[k] + real(2) * h;
           if constexpr (!PLAIN) {
             // ghost rows follow the stage value of the row next to them
-            if (kind[k] & 4u) outb[o - W4] = flux_bottom ? Yn + qb / fs : Tbot;
-            if (kind[k] & 8u) outb[o + W4] = top_dirichlet ? Ttop : Yn;
+            if (bottom) outb[o - EW] = flux_bottom ? Yn + qb / fs : Tbot;
+            if (top) outb[o + EW] = top_dirichlet ? Ttop : Yn;
           }
         } else {
           acc[k] = T0[k] + (dt / real(6)) * (acc[k] + h);
@@ -933,23 +921,21 @@ __global__ void __launch_bounds__(ENT)
   double v[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
-    if (!(kind[k] & 32u)) continue;
-    const int cell = t + ENT * k;
-    const int rr = cell / W3, cc = cell - rr * W3;
-    const int j = j0 - 3 + rr, gx = x0 - 3 + cc;
+    const int r = 1 + w + NW * k, j = j0 - 4 + r;
+    if (r < 4 || r >= 4 + TY || j >= nT || !lane_out) continue;
     const real Tn = acc[k];
     if (!isfinite(Tn)) err |= ERR_NONFINITE;
     Tout[(size_t)j * nx + gx] = Tn;
     v[0] += (double)rcv[k] * ((double)Tn - (double)T0[k]);
     v[1] += (double)rcv[k] * (double)Tn;
   }
-  if (err) flag_error(diag, err, step);
+  if (err) flag_error(diag, err, dstep_prev[0]);
   const double d6 = dtd / 6.0;
   v[2] = Qb * d6;
   v[3] = Qt * d6;
   v[4] = Qs * d6;
   if (nh == 0) v[4] = v[2];
-  block_sum_n<5, ENT / 64>(v, red);
+  block_sum_n<5, NW>(v, red);
   if (t == 0) {
     double* pe = hist_slot + 5 * tile;
     if (sub == 0) {
@@ -967,7 +953,7 @@ __global__ void __launch_bounds__(ENT)
   // their own columns (once per LB step).
   if (sub == 0 && j0 <= nT - 1 && nT - 1 < j0 + TY) {
     double ms[1] = {0.0};
-    if (top_open) {
+    if (top_open && w == 0 && lane_out) {
       real U = real(0);
       if (P.top_bc == TOP_CONVECTIVE) {
         // mean outflow velocity of the row below the top, from the collide partials
@@ -977,10 +963,9 @@ __global__ void __launch_bounds__(ENT)
         us /= nx;
         U = (real)(us > 0.0 ? us : 0.0);
       }
-      const int x = x0 + t;
-      if (t < TX && x < nx) ms[0] = outlet_column(P, x, U, fpost, topin, uxa, uya);
+      ms[0] = outlet_column(P, x0 + lane - 4, U, fpost, topin, uxa, uya);
     }
-    block_sum_n<1, ENT / 64>(ms, red);
+    block_sum_n<1, NW>(ms, red);
     if (t == 0) pmin_cur[tile % P.ntxE] = ms[0];
   }
 }

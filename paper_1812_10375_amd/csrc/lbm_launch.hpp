@@ -50,27 +50,24 @@ void step_once(lbm_ctx* h) {
   hipLaunchKernelGGL((lbmk::k_collide<real, f64 ? TY_F64 : TY_F32>), dim3(P.nblkL), dim3(NT), 0,
                      h->stream, P, fs, fd, topin, Tc, gw, rho, ux, uy, h->at<double>(L.mstate[prev]),
                      h->at<double>(L.pmin[prev]), h->at<double>(L.mstate[cur]),
-                     h->at<double>(L.partL[cur]), diag, (long long)h->step);
+                     h->at<double>(L.partL[cur]), diag, h->at<long long>(L.dstep[prev]),
+                     h->at<long long>(L.dstep[cur]));
   timing_end(h, tev);
   const double dt = 1.0 / h->cfg.n_sub;
   const bool iso = (h->cfg.flags & LBM_DIFF_ISOTROPIC) != 0;
-  constexpr int TX = f64 ? TXE_F64 : TXE_F32;
-  static_assert(EH_MAX == lbmk::EH_MAX, "tile height bound shared with the kernel");
   double* hslot = h->at<double>(L.hist) + (size_t)((h->hist_first + h->hist_count) % HIST) * P.nblkE * 5;
   for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
     const real* Tin = h->at<real>(L.T[h->tcur]);
     real* Tout = h->at<real>(L.T[1 - h->tcur]);
     tev = timing_begin(h, 1);
-    if (iso)
-      hipLaunchKernelGGL((lbmk::k_energy<real, TX, true>), dim3(P.nblkE), dim3(lbmk::ENT), 0,
-                         h->stream, P, Tin, Tout, rho, ux, uy, hslot, fd, topin,
-                         h->at<double>(L.partL[cur]), h->at<double>(L.pmin[cur]), diag, sub, dt,
-                         (long long)h->step);
-    else
-      hipLaunchKernelGGL((lbmk::k_energy<real, TX, false>), dim3(P.nblkE), dim3(lbmk::ENT), 0,
-                         h->stream, P, Tin, Tout, rho, ux, uy, hslot, fd, topin,
-                         h->at<double>(L.partL[cur]), h->at<double>(L.pmin[cur]), diag, sub, dt,
-                         (long long)h->step);
+#define LBM_E(ISO)                                                                               \
+  hipLaunchKernelGGL((lbmk::k_energy<real, ISO, E_NW, E_HMAX>), dim3(P.nblkE), dim3(E_NW * 64), 0, \
+                     h->stream, P, Tin, Tout, rho, ux, uy, hslot, fd, topin,                       \
+                     h->at<double>(L.partL[cur]), h->at<double>(L.pmin[cur]), diag, sub, dt,      \
+                     h->at<long long>(L.dstep[prev]))
+    if (iso) LBM_E(true);
+    else LBM_E(false);
+#undef LBM_E
     timing_end(h, tev);
     h->tcur = 1 - h->tcur;
   }
@@ -92,9 +89,15 @@ int scatter_state(lbm_ctx* h, const real* src, int src_is_rho) {
                      src_is_rho, h->at<real>(L.f[h->fcur]), h->at<real>(L.topin),
                      h->at<double>(L.partL[last]));
   finish_reductions<real>(h);
-  // the next collide kernel starts its mass bookkeeping from the summed mass
+  // the next collide kernel starts its mass bookkeeping from the summed mass, and its
+  // step count from the host's
   if (hipMemcpyAsync(h->at<double>(L.mstate[last]), &h->at<DevDiag>(L.diag)->mass, sizeof(double),
                      hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+    return LBM_EHIP;
+  h->step_staging = (long long)h->step;
+  if (hipMemcpyAsync(h->at<long long>(L.dstep[last]), &h->step_staging, sizeof(long long),
+                     hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
     return LBM_EHIP;
   return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EHIP;
 }

@@ -76,6 +76,8 @@ def library():
         L.lbm_write_field.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
         L.lbm_destroy.restype = C.c_int
         L.lbm_destroy.argtypes = [vp]
+        L.lbm_set_stream.restype = C.c_int
+        L.lbm_set_stream.argtypes = [vp, vp]
         L.lbm_set_kernel_timing.restype = C.c_int
         L.lbm_set_kernel_timing.argtypes = [vp, C.c_int]
         L.lbm_kernel_times.restype = C.c_int
@@ -173,6 +175,13 @@ class Lattice:
         if check and rc != 0:
             raise LbmError(rc, "lbm_observe")
         return d
+
+    def set_stream(self, stream):
+        """Enqueue later work on `stream` (a torch stream), e.g. a graph-capture stream."""
+        rc = library().lbm_set_stream(self.h, C.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise LbmError(rc, "lbm_set_stream")
+        self.stream = stream
 
     def set_kernel_timing(self, on):
         rc = library().lbm_set_kernel_timing(self.h, int(bool(on)))
