@@ -150,11 +150,15 @@ int lbm_init(const lbm_config *cfg, void *d_workspace, size_t ws_bytes, void *hi
              const double *rho0_host, const double *T0_host, lbm_ctx **out);
 
 /* Enqueue nsteps (>= 0) complete steps on the context's stream; never synchronises.
- * Every kernel argument repeats with period 2 steps except the diagnostics history slot,
- * which repeats every LBM_HISTORY_STEPS steps; a caller may therefore capture a multiple
- * of LBM_HISTORY_STEPS steps (starting right after lbm_observe) into a HIP graph and
- * replay it.  Device memory written: the workspace only; no memset or host copy is
- * enqueued by lbm_step. */
+ * Diagnostics of each step go to a device history of LBM_HISTORY_STEPS slots, folded
+ * (two small kernels) at the end of the step that fills it and by lbm_observe.
+ * Graph capture: every kernel argument repeats with period 2 steps except the history
+ * slot, so a caller may capture a multiple of LBM_HISTORY_STEPS steps that starts with
+ * an empty history (right after lbm_init, lbm_observe or lbm_write_field) into a HIP
+ * graph and replay it on the context's stream; each replay folds its own diagnostics.
+ * Replays advance the device's step counter only: call lbm_observe after them, before
+ * any other call on the context (it takes the step count from the device).
+ * Device memory written: the workspace only; no memset or host copy is enqueued. */
 #define LBM_HISTORY_STEPS 256
 int lbm_step(lbm_ctx *h, int64_t nsteps);
 

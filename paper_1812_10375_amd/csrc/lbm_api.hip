@@ -292,8 +292,15 @@ int lbm_observe(lbm_ctx* h, lbm_obs* out) {
   if (h->cfg.precision == LBM_F64) finish_reductions<double>(h);
   else finish_reductions<float>(h);
   DevDiag d;
-  if (hipMemcpyAsync(&d, dd, sizeof(d), hipMemcpyDeviceToHost, h->stream) != hipSuccess) return LBM_EHIP;
+  long long dstep = 0;
+  // the device's step counter is authoritative: graph replays advance it without the host
+  const int last = (int)((h->step + 1) & 1);
+  if (hipMemcpyAsync(&d, dd, sizeof(d), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipMemcpyAsync(&dstep, h->at<long long>(L.dstep[last]), sizeof(dstep), hipMemcpyDeviceToHost,
+                     h->stream) != hipSuccess)
+    return LBM_EHIP;
   if (hipStreamSynchronize(h->stream) != hipSuccess) return LBM_EHIP;
+  h->step = (int64_t)dstep;
   std::memset(out, 0, sizeof(*out));
   out->step = h->step;
   out->mass = d.mass;

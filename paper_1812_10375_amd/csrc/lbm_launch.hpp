@@ -30,9 +30,11 @@ void finish_reductions(lbm_ctx* h) {
 }
 
 // One lattice step: k_collide, then k_energy once per energy sub-step (Eq. 27).
+// A full history is folded at the end of the step that fills it, so any run of
+// HIST steps that starts with an empty history (after init, observe, a field write or
+// a multiple of HIST steps) carries its own fold and can be captured and replayed.
 template <typename real>
 void step_once(lbm_ctx* h) {
-  if (h->hist_count == HIST) finish_reductions<real>(h);
   const KParams& P = h->P;
   const Layout& L = h->L;
   constexpr bool f64 = sizeof(real) == 8;
@@ -74,6 +76,7 @@ void step_once(lbm_ctx* h) {
   h->hist_count += 1;
   h->fcur = 1 - h->fcur;
   h->step += 1;
+  if (h->hist_count == HIST) finish_reductions<real>(h);
 }
 
 // Store pre-collision populations (or the equilibrium at rest of a density field)
