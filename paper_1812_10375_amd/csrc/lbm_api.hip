@@ -67,7 +67,8 @@ Grids grids(const lbm_config* c, int ncu) {
   g.ntyL = (c->ny + ty - 1) / ty;
   g.ntxE = (c->nx + E_TXMAX - 1) / E_TXMAX;
   g.txE = (c->nx + g.ntxE - 1) / g.ntxE;
-  const int rows_min = (nT + E_HMAX - 1) / E_HMAX;
+  const int hmax = f64 ? E_HMAX : E_HMAX_F32;
+  const int rows_min = (nT + hmax - 1) / hmax;
   const int rows_max = (nT + E_HMIN - 1) / E_HMIN;
   int rows = rows_max;
   if (ncu > 0) {

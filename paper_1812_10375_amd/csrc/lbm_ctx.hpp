@@ -17,6 +17,13 @@ namespace lbmh {
 // grid so that the tiles fill the CUs in one round when the grid allows it.
 constexpr int TY_F32 = 16, TY_F64 = 8;
 constexpr int E_NW = 8, E_HMAX = 48, E_HMIN = 8, E_TXMAX = 56;
+// FP32 register-row energy kernel: E_RNW waves of E_BAND rows each, E_RWPE waves per
+// SIMD (two workgroups per CU)
+constexpr int E_RNW = 8, E_BAND = 7, E_RWPE = 4;
+// tallest FP32 energy tile (also within the LDS kernel's E_HMAX, used for FP32 with
+// the isotropic scheme)
+constexpr int E_HMAX_F32 = E_RNW * E_BAND - 8;
+static_assert(E_HMAX_F32 <= E_HMAX && E_HMAX_F32 >= E_HMIN, "FP32 energy tile height");
 // energy workgroups resident per CU (LDS: 57 KB per FP32 workgroup, 115 KB per FP64)
 constexpr int E_PER_CU_F32 = 2, E_PER_CU_F64 = 1;
 // Steps of energy partials kept before they are folded into the diagnostics.

@@ -1,0 +1,344 @@
+// lbm_energy_f32.hpp -- FP32 temperature update with register-resident rows.
+//
+// Same tile, four-cell halo and fused RK4 stages as k_energy (Eq. 17-18, Eq. 19,
+// Eq. 22-27), arranged for the vector ALU instead of LDS.  Each wave owns a band of B
+// consecutive tile rows and keeps them in registers, lane = tile column.  West and east
+// neighbours come from whole-wavefront DPP lane shifts, north and south neighbours from
+// the neighbouring register row.  Only the two edge rows of each band pass through LDS,
+// once per stage.  At set-up the right-hand side of Eq. 17 at a cell is folded into one
+// nine-point stencil with eight coefficients, since everything but the latent term is
+// linear in T with rho and u frozen:
+//   h = cP T + cE E + cW W + cN N + cS S + aP (NE - SW) + aM (SE - NW) - l2 sqrt(T)
+// Diffusion (Eq. 22-26) gives g_f = lambda_f / (rho c_v) per face f; advection with the
+// Eq. 19 gradient gives aX = -u_x/3, aY = -u_y/3, aP = -(u_x + u_y)/12,
+// aM = -(u_x - u_y)/12; the latent term -(T/(rho c_v)) (dp/dT)_v div u of Eq. 17 with
+// Eq. 28, using T phi'(T) = -kappa s (1 + kappa - kappa s) and s = sqrt(T/T_c), is
+// -l1 T - l2 sqrt(T) with l1 = C div(u) (A - B kappa^2/T_c) and
+// l2 = C div(u) B kappa (1 + kappa)/sqrt(T_c), where C = 1/(rho c_v), A = rho R/(1 - b rho)
+// and B = a rho^2/(1 + 2 b rho - b^2 rho^2).  Hence cE = g_E + aX, cW = g_W - aX,
+// cN = g_N + aY, cS = g_S - aY and cP = -(g_E + g_W + g_N + g_S) - l1.
+#pragma once
+#include "lbm_kernels.hpp"
+
+namespace lbmk {
+
+// Value held by lane + 1 (east) / lane - 1 (west) of the wavefront: DPP wave_shl:1 and
+// wave_shr:1.  The end lanes read 0; they are halo lanes whose results are never used.
+__device__ __forceinline__ float lane_east(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_west(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+
+// Tile: txE (<= 56) columns by tyE rows of the temperature grid, with tyE + 8 <= NW * B.
+// Lane c holds global column x0 - 4 + c (periodic); tile row r holds T row j0 - 4 + r;
+// wave w owns tile rows [w B, w B + B).  Stage s is valid on tile rows [1 + s, tyE + 7 - s)
+// and lanes [1 + s, 63 - s); cells outside that cone are computed or left as they are
+// and never reach a written cell.
+template <int NW, int B>
+struct RowsShared {
+  float edge[2][NW][2][64];  // [stage parity][wave][bottom/top row][lane]
+  float rcv[NW][B][64];      // rho c_v of the band rows (energy partials)
+  double red[RED_SIZE];
+};
+
+// The tile work.  PLAIN: every row of the tile (halo included) is a fluid row away from
+// both boundaries, so no row needs boundary handling and none is skipped.
+template <int NW, int B, bool PLAIN>
+__device__ __forceinline__ void energy_rows_tile(
+    const KParams& P, RowsShared<NW, B>& sh, const float* __restrict__ Tin, float* __restrict__ Tout,
+    const float* __restrict__ rho, const float* __restrict__ uxa, const float* __restrict__ uya,
+    double* __restrict__ hist_slot, DevDiag* __restrict__ diag, int sub, double dtd,
+    const long long* __restrict__ dstep_prev, int tile, int x0, int j0) {
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int nx = P.nx, nT = P.nT, nh = P.nh;
+  const int TX = P.txE, TY = P.tyE, H4 = TY + 8;
+  const int gx = wrapm(x0 - 4 + lane, nx);
+  const int r0 = w * B;          // first tile row of this wave's band
+  const int jb = j0 - 4 + r0;    // its temperature row
+  const bool wave_live = r0 < H4;
+  const bool top_open = P.top_bc != TOP_WALL;
+  const bool do_adv = !(P.flags & NO_ADVECTION), do_lat = !(P.flags & NO_LATENT);
+  const bool flux_bottom = P.bottom_tbc == TBC_FLUX, top_dirichlet = P.top_tbc == TBC_DIRICHLET;
+  const float cvk = (float)P.cvk, cv = (float)P.cv, lamw = (float)P.lambda_w;
+  const float inv3 = 1.f / 3.f, inv12 = 1.f / 12.f;
+
+  // ---- load temperature rows jb - 1 .. jb + B with rho and u (u = 0 on solids, and
+  // zero-gradient above an open top) ----
+  float lT[B + 2], lR[B + 2], lU[B + 2], lV[B + 2];
+  if constexpr (PLAIN) {
+    // rows outside the tile are clamped into the fluid rows; their values are unused
+#pragma unroll
+    for (int q = 0; q < B + 2; ++q) {
+      const int j = min(max(jb - 1 + q, nh), nT - 1);
+      lT[q] = Tin[(size_t)j * nx + gx];
+      const size_t n = (size_t)(j - nh) * nx + gx;
+      lR[q] = rho[n];
+      lU[q] = uxa[n];
+      lV[q] = uya[n];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < B + 2; ++q) {
+      const int j = jb - 1 + q;
+      lT[q] = 0.f; lR[q] = 0.f; lU[q] = 0.f; lV[q] = 0.f;
+      if (r0 - 1 + q >= H4) continue;
+      if (j >= 0 && j < nT) {
+        lT[q] = Tin[(size_t)j * nx + gx];
+        if (j >= nh) {
+          const size_t n = (size_t)(j - nh) * nx + gx;
+          lR[q] = rho[n];
+          lU[q] = uxa[n];
+          lV[q] = uya[n];
+        }
+      } else if (j == nT && top_open) {
+        const size_t n = (size_t)(P.ny - 1) * nx + gx;
+        lU[q] = uxa[n];
+        lV[q] = uya[n];
+      }
+    }
+  }
+
+  // ---- conductivities and faces (Eq. 25); a face to a ghost row takes the inner lambda ----
+  float lam[B + 2];
+#pragma unroll
+  for (int q = 0; q < B + 2; ++q) {
+    const int j = jb - 1 + q;
+    if constexpr (PLAIN) lam[q] = lR[q] * cvk;
+    else lam[q] = (j >= nh && j < nT) ? lR[q] * cvk : ((j >= 0 && j < nh) ? lamw : 1.f);
+  }
+  float fN[B + 1];  // face between loaded rows q and q + 1
+#pragma unroll
+  for (int q = 0; q < B + 1; ++q) {
+    const int j = jb - 1 + q;
+    const float a = lam[q], b = lam[q + 1];
+    const float hm = 2.f * a * b * __builtin_amdgcn_rcpf(a + b);
+    if constexpr (PLAIN) fN[q] = hm;
+    else fN[q] = (j == -1) ? b : ((j == nT - 1) ? a : hm);
+  }
+  // faces and ghost offsets that the boundary rows need (heat-flux diagnostics)
+  float gq = 0.f, fq0 = 0.f, fqt = 0.f, fqh = 0.f;
+  if constexpr (!PLAIN) {
+#pragma unroll
+    for (int q = 0; q < B + 2; ++q) {
+      const int j = jb - 1 + q;
+      if (j == 0) {
+        fq0 = lam[q];
+        gq = (float)P.q_bottom * __builtin_amdgcn_rcpf(lam[q]);
+      }
+      if (j == nT - 1) fqt = lam[q];
+      if (q > 0 && j == nh && nh > 0) fqh = fN[q - 1];
+    }
+  }
+
+  // ---- per-cell coefficients of the band rows ----
+  float uxE[B + 2], uxW[B + 2], uyE[B + 2], uyW[B + 2];
+#pragma unroll
+  for (int q = 0; q < B + 2; ++q) {
+    uxE[q] = lane_east(lU[q]);
+    uxW[q] = lane_west(lU[q]);
+    uyE[q] = lane_east(lV[q]);
+    uyW[q] = lane_west(lV[q]);
+  }
+  const float kk2 = (float)(P.kappa * P.kappa * P.inv_Tc);
+  const float kl2 = (float)(P.kappa * (1.0 + P.kappa) * sqrt(P.inv_Tc));
+  float Y[B], T0[B], acc[B];
+  float cP[B], cE[B], cW[B], cN[B], cS[B], aP[B], aM[B], l2[B];
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    const int q = k + 1, j = jb + k;
+    const bool fluid = PLAIN || (j >= nh && j < nT);
+    const float r = lR[q];
+    float C, rc;
+    if (fluid) {
+      rc = r * cv;
+      C = __builtin_amdgcn_rcpf(rc);
+    } else {
+      rc = (float)P.rcw;
+      C = (float)P.inv_rcw;
+    }
+    sh.rcv[w][k][lane] = rc;
+    const float lE = lane_east(lam[q]);
+    const float fe = 2.f * lam[q] * lE * __builtin_amdgcn_rcpf(lam[q] + lE);
+    const float ge = C * fe, gw = C * lane_west(fe), gn = C * fN[q], gs = C * fN[q - 1];
+    float ax = 0.f, ay = 0.f, l1 = 0.f;
+    aP[k] = 0.f; aM[k] = 0.f; l2[k] = 0.f;
+    if (fluid) {
+      const float ux = lU[q], uy = lV[q];
+      if (do_adv) {
+        ax = -ux * inv3;
+        ay = -uy * inv3;
+        aP[k] = -(ux + uy) * inv12;
+        aM[k] = -(ux - uy) * inv12;
+      }
+      if (do_lat) {
+        // div u by Eq. 19
+        const float dudx = (uxE[q] - uxW[q]) * inv3 + ((uxE[q + 1] - uxW[q - 1]) + (uxE[q - 1] - uxW[q + 1])) * inv12;
+        const float dvdy = (lV[q + 1] - lV[q - 1]) * inv3 + ((uyE[q + 1] - uyW[q - 1]) + (uyW[q + 1] - uyE[q - 1])) * inv12;
+        const float br = (float)P.b * r;
+        const float Ad = r * (float)P.R * __builtin_amdgcn_rcpf(1.f - br);
+        const float Bd = (float)P.a * r * r * __builtin_amdgcn_rcpf(1.f + 2.f * br - br * br);
+        const float cd = C * (dudx + dvdy);
+        l1 = cd * (Ad - Bd * kk2);
+        l2[k] = cd * Bd * kl2;
+      }
+    }
+    cE[k] = ge + ax;
+    cW[k] = gw - ax;
+    cN[k] = gn + ay;
+    cS[k] = gs - ay;
+    cP[k] = -(((ge + gw) + gn) + gs) - l1;
+    Y[k] = lT[q];
+    T0[k] = lT[q];
+    acc[k] = 0.f;
+  }
+
+  // ---- four RK stages (Eq. 18) ----
+  const float dt = (float)dtd, Tbot = (float)P.T_bottom, Ttop = (float)P.T_top, qb = (float)P.q_bottom;
+  const float dt2 = 0.5f * dt, dt6 = (float)(dtd / 6.0);
+  const bool lane_out = lane >= 4 && lane < 4 + TX && x0 + lane - 4 < nx;
+  float eS = lT[0], eN = lT[B + 1];  // rows below and above the band
+  double Qb = 0.0, Qt = 0.0, Qs = 0.0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if constexpr (!PLAIN) {
+      // ghost rows take their stage value from the row next to them
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int j = jb + k;
+        if (j == -1) Y[k] = flux_bottom ? ((k + 1 < B ? Y[k + 1] : eN) + gq) : Tbot;
+        if (j == nT) Y[k] = top_dirichlet ? Ttop : (k > 0 ? Y[k - 1] : eS);
+      }
+      if (jb == 0) eS = flux_bottom ? Y[0] + gq : Tbot;
+      if (jb + B == nT) eN = top_dirichlet ? Ttop : Y[B - 1];
+    }
+    const float wgt = (s == 0 || s == 3) ? 1.f : 2.f;
+    if (wave_live) {
+      float s0 = eS, sE = lane_east(eS), sW = lane_west(eS);
+      float c0 = Y[0], wE = lane_east(c0), wW = lane_west(c0);
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const float n0 = (k + 1 < B) ? Y[k + 1] : eN;
+        const float nE = lane_east(n0), nW = lane_west(n0);
+        const int j = jb + k;
+        const bool active = PLAIN || ((r0 + k < H4) && j >= 0 && j < nT);
+        if (active) {
+          const float Tp = c0;
+          float h = cP[k] * Tp + cE[k] * wE + cW[k] * wW + cN[k] * n0 + cS[k] * s0;
+          h += aP[k] * (nE - sW) + aM[k] * (sE - nW);
+          h -= l2[k] * __builtin_amdgcn_sqrtf(Tp);
+          if constexpr (!PLAIN) {
+            const int r = r0 + k;
+            if (r >= 4 && r < 4 + TY && lane_out) {
+              if (j == 0) Qb += (double)(wgt * (flux_bottom ? qb : fq0 * (s0 - Tp)));
+              if (j == nT - 1 && top_dirichlet) Qt += (double)(wgt * (fqt * (n0 - Tp)));
+              if (nh > 0 && j == nh) Qs += (double)(wgt * (fqh * (s0 - Tp)));
+            }
+          }
+          if (s == 0) {
+            Y[k] = T0[k] + dt2 * h;
+            acc[k] = h;
+          } else if (s < 3) {
+            Y[k] = T0[k] + ((s == 2) ? dt : dt2) * h;
+            acc[k] = acc[k] + 2.f * h;
+          } else {
+            Y[k] = T0[k] + dt6 * (acc[k] + h);
+          }
+        }
+        s0 = c0; sE = wE; sW = wW;
+        c0 = n0; wE = nE; wW = nW;
+      }
+    }
+    if (s < 3) {
+      sh.edge[s & 1][w][0][lane] = Y[0];
+      sh.edge[s & 1][w][1][lane] = Y[B - 1];
+      __syncthreads();
+      eS = w > 0 ? sh.edge[s & 1][w - 1][1][lane] : Y[0];
+      eN = w < NW - 1 ? sh.edge[s & 1][w + 1][0][lane] : Y[B - 1];
+    }
+  }
+
+  // ---- write T^{n+1}, FP64 partials ----
+  unsigned err = 0;
+  double v[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    const int r = r0 + k, j = jb + k;
+    if (r < 4 || r >= 4 + TY || j >= nT || !lane_out) continue;
+    const float Tn = Y[k];
+    if (!isfinite(Tn)) err |= ERR_NONFINITE;
+    Tout[(size_t)j * nx + gx] = Tn;
+    const double rc = (double)sh.rcv[w][k][lane];
+    v[0] += rc * ((double)Tn - (double)T0[k]);
+    v[1] += rc * (double)Tn;
+  }
+  if (err) flag_error(diag, err, dstep_prev[0]);
+  const double d6 = dtd / 6.0;
+  v[2] = Qb * d6;
+  v[3] = Qt * d6;
+  v[4] = Qs * d6;
+  if (nh == 0) v[4] = v[2];
+  block_sum_n<5, NW>(v, sh.red);
+  if (t == 0) {
+    double* pe = hist_slot + 5 * tile;
+    if (sub == 0) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) pe[k] = v[k];
+    } else {
+      pe[0] += v[0];
+      pe[1] = v[1];
+      pe[2] += v[2];
+      pe[3] += v[3];
+      pe[4] += v[4];
+    }
+  }
+}
+
+template <int NW, int B, int WPE>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
+    k_energy_rows(const KParams P, const float* __restrict__ Tin, float* __restrict__ Tout,
+                  const float* __restrict__ rho, const float* __restrict__ uxa,
+                  const float* __restrict__ uya, double* __restrict__ hist_slot,
+                  const float* __restrict__ fpost, float* __restrict__ topin,
+                  const double* __restrict__ partL_cur, double* __restrict__ pmin_cur,
+                  DevDiag* __restrict__ diag, int sub, double dtd,
+                  const long long* __restrict__ dstep_prev) {
+  __shared__ RowsShared<NW, B> sh;
+  const int nT = P.nT, TY = P.tyE;
+  const int tile = xcd_tile(blockIdx.x, P.nblkE);
+  const int x0 = (tile % P.ntxE) * P.txE, j0 = (tile / P.ntxE) * TY;
+  const bool plain_tile = (j0 - 4 >= P.nh) && (j0 + TY + 3 <= nT - 1);
+  if (plain_tile)
+    energy_rows_tile<NW, B, true>(P, sh, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
+                                  tile, x0, j0);
+  else
+    energy_rows_tile<NW, B, false>(P, sh, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
+                                   tile, x0, j0);
+
+  // Tiles holding the top fluid row set the open-top inflow of the next step for
+  // their own columns (once per LB step).
+  if (sub == 0 && j0 <= nT - 1 && nT - 1 < j0 + TY) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int nx = P.nx;
+    const bool lane_out = lane >= 4 && lane < 4 + P.txE && x0 + lane - 4 < nx;
+    double ms[1] = {0.0};
+    if (P.top_bc != TOP_WALL && w == 0 && lane_out) {
+      float U = 0.f;
+      if (P.top_bc == TOP_CONVECTIVE) {
+        // mean outflow velocity of the row below the top, from the collide partials
+        const int ry = (P.ny - 2) / P.tyL;
+        double us = 0.0;
+        for (int bx = 0; bx < P.ntxL; ++bx) us += partL_cur[3 * (ry * P.ntxL + bx) + 2];
+        us /= nx;
+        U = (float)(us > 0.0 ? us : 0.0);
+      }
+      ms[0] = outlet_column(P, x0 + lane - 4, U, fpost, topin, uxa, uya);
+    }
+    block_sum_n<1, NW>(ms, sh.red);
+    if (t == 0) pmin_cur[tile % P.ntxE] = ms[0];
+  }
+}
+
+}  // namespace lbmk

@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "lbm_ctx.hpp"
+#include "lbm_energy_f32.hpp"
 #include "lbm_kernels.hpp"
 
 namespace lbmh {
@@ -68,7 +69,11 @@ void step_once(lbm_ctx* h) {
                      h->at<double>(L.partL[cur]), h->at<double>(L.pmin[cur]), diag, sub, dt,      \
                      h->at<long long>(L.dstep[prev]))
     if (iso) LBM_E(true);
-    else LBM_E(false);
+    else if constexpr (f64) LBM_E(false);
+    else
+      hipLaunchKernelGGL((lbmk::k_energy_rows<E_RNW, E_BAND, E_RWPE>), dim3(P.nblkE), dim3(E_RNW * 64), 0, h->stream, P,
+                         Tin, Tout, rho, ux, uy, hslot, fd, topin, h->at<double>(L.partL[cur]),
+                         h->at<double>(L.pmin[cur]), diag, sub, dt, h->at<long long>(L.dstep[prev]));
 #undef LBM_E
     timing_end(h, tev);
     h->tcur = 1 - h->tcur;

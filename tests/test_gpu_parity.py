@@ -119,3 +119,40 @@ def test_fp32_pool_boiling_full_size_first_steps():
     # benchmark times, against the oracle over its first steps
     sc = S.pool_boiling()
     _check32(sc, 20)
+
+
+def _check32_heat(sc, steps, rel=1e-3):
+    res, e = _check32(sc, steps)
+    og, oo = res["gpu_obs"], res["orc_obs"]
+    scale = max(abs(oo["Q_bottom_cum"]), abs(oo["Q_top_cum"]), 1e-30)
+    for k in ("Q_bottom_cum", "Q_top_cum", "Q_surface_cum", "dE_cum"):
+        assert abs(og[k] - oo[k]) <= rel * scale, (k, og[k], oo[k])
+    return res, e
+
+
+def test_fp32_interface_conduction_walls():
+    # Dirichlet walls below and above (Sec. 3.2 setting), FP32 fields
+    sc = S.interface_conduction(exact_energy=False, steps=1000)
+    sc["precision"] = "f32"
+    _check32_heat(sc, 1000)
+
+
+def test_fp32_tall_domain_with_interior_tiles():
+    sc = S.pool_boiling(nx=40, ny=200, heater_rows=5, n_sites=1, min_spacing=8, seed=9)
+    _check32_heat(sc, 300)
+
+
+def test_fp32_energy_substeps_and_flux_bottom():
+    sc = S.film_evaporation(nx=40, ny=30, film=10, seed=3, precision="f32")
+    sc["n_sub"] = 3
+    sc["bottom_tbc"] = "flux"
+    sc["q_bottom"] = 2e-4
+    sc["heater_rows"] = 4
+    sc["T0"] = np.full((34, 40), S.T_SAT)
+    _check32_heat(sc, 100)
+
+
+@pytest.mark.parametrize("nx,ny,nh", [(1, 12, 0), (3, 2, 2), (65, 17, 1), (130, 90, 25)])
+def test_fp32_degenerate_and_ragged_shapes(nx, ny, nh):
+    sc = S.pool_boiling(nx=nx, ny=ny, heater_rows=nh, n_sites=0, seed=1, precision="f32")
+    _check32(sc, 50)
