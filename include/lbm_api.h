@@ -66,7 +66,9 @@ enum {
 /*
  * Configuration.  Set struct_size = sizeof(lbm_config) and abi_version =
  * LBM_ABI_VERSION.  Units are lattice units (c = dx = dt = 1).
- *   nx, ny, heater_rows   lattice size; nx, ny >= 1 (ny >= 2 with an open top)
+ *   nx, ny, heater_rows   lattice size; nx, ny >= 1 (ny >= 2 with an open top); one field
+ *                         of nx (ny + heater_rows) values must stay below 4 GiB (FP32: about
+ *                         1.07e9 nodes, FP64: about 5.4e8)
  *   n_sub                 N of Eq. 27 (energy sub-steps per LB step), >= 1
  *   precision             LBM_F32 or LBM_F64 (the Peng-Robinson EOS of Eq. 7/28 and all
  *                         reductions are FP64 in both)

@@ -26,8 +26,10 @@ bool valid_config(const lbm_config* c) {
   if (c->struct_size != sizeof(lbm_config) || c->abi_version != LBM_ABI_VERSION) return false;
   if (c->nx < 1 || c->ny < 1 || c->heater_rows < 0 || c->n_sub < 1) return false;
   if (c->nx > (1 << 20) || c->ny > (1 << 20) || c->heater_rows > (1 << 20)) return false;
-  if ((double)c->nx * (double)(c->ny + c->heater_rows) > 4.0e9) return false;
   if (c->precision != LBM_F32 && c->precision != LBM_F64) return false;
+  // one field plane is addressed with 32-bit byte offsets
+  const double vbytes = c->precision == LBM_F64 ? 8.0 : 4.0;
+  if ((double)c->nx * (double)(c->ny + c->heater_rows) * vbytes >= 4294967296.0) return false;
   if (c->top_bc < LBM_TOP_WALL || c->top_bc > LBM_TOP_CONVECTIVE) return false;
   if (c->top_bc != LBM_TOP_WALL && c->ny < 2) return false;
   if (c->bottom_tbc != LBM_TBC_DIRICHLET && c->bottom_tbc != LBM_TBC_FLUX) return false;
@@ -163,6 +165,7 @@ KParams make_params(const lbm_config* c, int ncu) {
   P.phi_sat = ssat * ssat;
   P.T_sat = c->T_sat;
   P.inv3 = 1.0 / 3.0;
+  P.two_G = 2.0 / c->G;
   P.rho_l = c->rho_l;
   P.rho_v = c->rho_v;
   P.inv_drho = 1.0 / (c->rho_l - c->rho_v);
@@ -192,6 +195,12 @@ KParams make_params(const lbm_config* c, int ncu) {
   P.T_bottom = c->T_bottom;
   P.T_top = c->T_top;
   P.q_bottom = c->q_bottom;
+  P.e_k2 = (float)(2.0 * c->k);
+  P.e_g1a = (float)(P.R / c->cv);
+  P.e_g1b = (float)(P.a * kap * kap / Tc / c->cv);
+  P.e_g2a = (float)(P.a * kap * (1.0 + kap) / std::sqrt(Tc) / c->cv);
+  P.e_kk2 = (float)(kap * kap / Tc);
+  P.e_kl2 = (float)(kap * (1.0 + kap) / std::sqrt(Tc));
   return P;
 }
 

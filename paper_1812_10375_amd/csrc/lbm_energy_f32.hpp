@@ -73,11 +73,11 @@ __device__ __forceinline__ void energy_rows_tile(
 #pragma unroll
     for (int q = 0; q < B + 2; ++q) {
       const int j = min(max(jb - 1 + q, nh), nT - 1);
-      lT[q] = Tin[(size_t)j * nx + gx];
-      const size_t n = (size_t)(j - nh) * nx + gx;
-      lR[q] = rho[n];
-      lU[q] = uxa[n];
-      lV[q] = uya[n];
+      lT[q] = ld32(Tin, (unsigned)j * (unsigned)nx + gx);
+      const unsigned n = (unsigned)(j - nh) * (unsigned)nx + gx;
+      lR[q] = ld32(rho, n);
+      lU[q] = ld32(uxa, n);
+      lV[q] = ld32(uya, n);
     }
   } else {
 #pragma unroll
@@ -101,26 +101,83 @@ __device__ __forceinline__ void energy_rows_tile(
     }
   }
 
-  // ---- conductivities and faces (Eq. 25); a face to a ghost row takes the inner lambda ----
-  float lam[B + 2];
+  // ---- per-cell coefficients of the band rows ----
+  float uxE[B + 2], uxW[B + 2], uyE[B + 2], uyW[B + 2];
 #pragma unroll
   for (int q = 0; q < B + 2; ++q) {
-    const int j = jb - 1 + q;
-    if constexpr (PLAIN) lam[q] = lR[q] * cvk;
-    else lam[q] = (j >= nh && j < nT) ? lR[q] * cvk : ((j >= 0 && j < nh) ? lamw : 1.f);
+    uxE[q] = lane_east(lU[q]);
+    uxW[q] = lane_west(lU[q]);
+    uyE[q] = lane_east(lV[q]);
+    uyW[q] = lane_west(lV[q]);
   }
-  float fN[B + 1];  // face between loaded rows q and q + 1
-#pragma unroll
-  for (int q = 0; q < B + 1; ++q) {
-    const int j = jb - 1 + q;
-    const float a = lam[q], b = lam[q + 1];
-    const float hm = 2.f * a * b * __builtin_amdgcn_rcpf(a + b);
-    if constexpr (PLAIN) fN[q] = hm;
-    else fN[q] = (j == -1) ? b : ((j == nT - 1) ? a : hm);
-  }
-  // faces and ghost offsets that the boundary rows need (heat-flux diagnostics)
+  float Y[B], T0[B], acc[B];
+  float cP[B], cE[B], cW[B], cN[B], cS[B], aP[B], aM[B], l2[B];
   float gq = 0.f, fq0 = 0.f, fqt = 0.f, fqh = 0.f;
-  if constexpr (!PLAIN) {
+  // div u at band row k by Eq. 19
+  auto divu = [&](int q) {
+    const float dudx = (uxE[q] - uxW[q]) * inv3 + ((uxE[q + 1] - uxW[q - 1]) + (uxE[q - 1] - uxW[q + 1])) * inv12;
+    const float dvdy = (lV[q + 1] - lV[q - 1]) * inv3 + ((uyE[q + 1] - uyW[q - 1]) + (uyW[q + 1] - uyE[q - 1])) * inv12;
+    return dudx + dvdy;
+  };
+  if constexpr (PLAIN) {
+    // All fluid: with lambda = rho c_v k, a face coefficient lambda_f / (rho_P c_v) of
+    // Eq. 25 is 2 k rho_nb / (rho_P + rho_nb); the latent factors A/(rho c_v) and
+    // B/(rho c_v) share the denominator (1 - b rho)(1 + 2 b rho - b^2 rho^2).
+    const float k2 = P.e_k2, g1a = P.e_g1a, g1b = P.e_g1b, g2a = P.e_g2a;
+    const float bb = (float)P.b;
+    float rN[B + 1];  // 1 / (rho_q + rho_{q+1})
+#pragma unroll
+    for (int q = 0; q < B + 1; ++q) rN[q] = __builtin_amdgcn_rcpf(lR[q] + lR[q + 1]);
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int q = k + 1;
+      const float r = lR[q];
+      sh.rcv[w][k][lane] = r * cv;
+      const float rE = lane_east(r), rWv = lane_west(r);
+      const float iE = __builtin_amdgcn_rcpf(r + rE);
+      const float ge = k2 * rE * iE, gw = k2 * rWv * lane_west(iE);
+      const float gn = k2 * lR[q + 1] * rN[q], gs = k2 * lR[q - 1] * rN[q - 1];
+      float ax = 0.f, ay = 0.f, l1 = 0.f;
+      aP[k] = 0.f; aM[k] = 0.f; l2[k] = 0.f;
+      const float ux = lU[q], uy = lV[q];
+      if (do_adv) {
+        ax = -ux * inv3;
+        ay = -uy * inv3;
+        aP[k] = -(ux + uy) * inv12;
+        aM[k] = -(ux - uy) * inv12;
+      }
+      if (do_lat) {
+        const float br = bb * r, d1 = 1.f - br, d2 = 1.f + 2.f * br - br * br;
+        const float dv = divu(q) * __builtin_amdgcn_rcpf(d1 * d2);
+        l1 = dv * (g1a * d2 - g1b * r * d1);
+        l2[k] = dv * (g2a * r * d1);
+      }
+      cE[k] = ge + ax;
+      cW[k] = gw - ax;
+      cN[k] = gn + ay;
+      cS[k] = gs - ay;
+      cP[k] = -(((ge + gw) + gn) + gs) - l1;
+      Y[k] = lT[q];
+      T0[k] = lT[q];
+      acc[k] = 0.f;
+    }
+  } else {
+    // conductivities and faces (Eq. 25); a face to a ghost row takes the inner lambda
+    float lam[B + 2];
+#pragma unroll
+    for (int q = 0; q < B + 2; ++q) {
+      const int j = jb - 1 + q;
+      lam[q] = (j >= nh && j < nT) ? lR[q] * cvk : ((j >= 0 && j < nh) ? lamw : 1.f);
+    }
+    float fN[B + 1];  // face between loaded rows q and q + 1
+#pragma unroll
+    for (int q = 0; q < B + 1; ++q) {
+      const int j = jb - 1 + q;
+      const float a = lam[q], b = lam[q + 1];
+      const float hm = 2.f * a * b * __builtin_amdgcn_rcpf(a + b);
+      fN[q] = (j == -1) ? b : ((j == nT - 1) ? a : hm);
+    }
+    // faces and ghost offsets that the boundary rows need (heat-flux diagnostics)
 #pragma unroll
     for (int q = 0; q < B + 2; ++q) {
       const int j = jb - 1 + q;
@@ -131,68 +188,52 @@ __device__ __forceinline__ void energy_rows_tile(
       if (j == nT - 1) fqt = lam[q];
       if (q > 0 && j == nh && nh > 0) fqh = fN[q - 1];
     }
-  }
-
-  // ---- per-cell coefficients of the band rows ----
-  float uxE[B + 2], uxW[B + 2], uyE[B + 2], uyW[B + 2];
+    const float kk2 = P.e_kk2, kl2 = P.e_kl2;
 #pragma unroll
-  for (int q = 0; q < B + 2; ++q) {
-    uxE[q] = lane_east(lU[q]);
-    uxW[q] = lane_west(lU[q]);
-    uyE[q] = lane_east(lV[q]);
-    uyW[q] = lane_west(lV[q]);
-  }
-  const float kk2 = (float)(P.kappa * P.kappa * P.inv_Tc);
-  const float kl2 = (float)(P.kappa * (1.0 + P.kappa) * sqrt(P.inv_Tc));
-  float Y[B], T0[B], acc[B];
-  float cP[B], cE[B], cW[B], cN[B], cS[B], aP[B], aM[B], l2[B];
-#pragma unroll
-  for (int k = 0; k < B; ++k) {
-    const int q = k + 1, j = jb + k;
-    const bool fluid = PLAIN || (j >= nh && j < nT);
-    const float r = lR[q];
-    float C, rc;
-    if (fluid) {
-      rc = r * cv;
-      C = __builtin_amdgcn_rcpf(rc);
-    } else {
-      rc = (float)P.rcw;
-      C = (float)P.inv_rcw;
-    }
-    sh.rcv[w][k][lane] = rc;
-    const float lE = lane_east(lam[q]);
-    const float fe = 2.f * lam[q] * lE * __builtin_amdgcn_rcpf(lam[q] + lE);
-    const float ge = C * fe, gw = C * lane_west(fe), gn = C * fN[q], gs = C * fN[q - 1];
-    float ax = 0.f, ay = 0.f, l1 = 0.f;
-    aP[k] = 0.f; aM[k] = 0.f; l2[k] = 0.f;
-    if (fluid) {
-      const float ux = lU[q], uy = lV[q];
-      if (do_adv) {
-        ax = -ux * inv3;
-        ay = -uy * inv3;
-        aP[k] = -(ux + uy) * inv12;
-        aM[k] = -(ux - uy) * inv12;
+    for (int k = 0; k < B; ++k) {
+      const int q = k + 1, j = jb + k;
+      const bool fluid = j >= nh && j < nT;
+      const float r = lR[q];
+      float C, rc;
+      if (fluid) {
+        rc = r * cv;
+        C = __builtin_amdgcn_rcpf(rc);
+      } else {
+        rc = (float)P.rcw;
+        C = (float)P.inv_rcw;
       }
-      if (do_lat) {
-        // div u by Eq. 19
-        const float dudx = (uxE[q] - uxW[q]) * inv3 + ((uxE[q + 1] - uxW[q - 1]) + (uxE[q - 1] - uxW[q + 1])) * inv12;
-        const float dvdy = (lV[q + 1] - lV[q - 1]) * inv3 + ((uyE[q + 1] - uyW[q - 1]) + (uyW[q + 1] - uyE[q - 1])) * inv12;
-        const float br = (float)P.b * r;
-        const float Ad = r * (float)P.R * __builtin_amdgcn_rcpf(1.f - br);
-        const float Bd = (float)P.a * r * r * __builtin_amdgcn_rcpf(1.f + 2.f * br - br * br);
-        const float cd = C * (dudx + dvdy);
-        l1 = cd * (Ad - Bd * kk2);
-        l2[k] = cd * Bd * kl2;
+      sh.rcv[w][k][lane] = rc;
+      const float lE = lane_east(lam[q]);
+      const float fe = 2.f * lam[q] * lE * __builtin_amdgcn_rcpf(lam[q] + lE);
+      const float ge = C * fe, gw = C * lane_west(fe), gn = C * fN[q], gs = C * fN[q - 1];
+      float ax = 0.f, ay = 0.f, l1 = 0.f;
+      aP[k] = 0.f; aM[k] = 0.f; l2[k] = 0.f;
+      if (fluid) {
+        const float ux = lU[q], uy = lV[q];
+        if (do_adv) {
+          ax = -ux * inv3;
+          ay = -uy * inv3;
+          aP[k] = -(ux + uy) * inv12;
+          aM[k] = -(ux - uy) * inv12;
+        }
+        if (do_lat) {
+          const float br = (float)P.b * r;
+          const float Ad = r * (float)P.R * __builtin_amdgcn_rcpf(1.f - br);
+          const float Bd = (float)P.a * r * r * __builtin_amdgcn_rcpf(1.f + 2.f * br - br * br);
+          const float cd = C * divu(q);
+          l1 = cd * (Ad - Bd * kk2);
+          l2[k] = cd * Bd * kl2;
+        }
       }
+      cE[k] = ge + ax;
+      cW[k] = gw - ax;
+      cN[k] = gn + ay;
+      cS[k] = gs - ay;
+      cP[k] = -(((ge + gw) + gn) + gs) - l1;
+      Y[k] = lT[q];
+      T0[k] = lT[q];
+      acc[k] = 0.f;
     }
-    cE[k] = ge + ax;
-    cW[k] = gw - ax;
-    cN[k] = gn + ay;
-    cS[k] = gs - ay;
-    cP[k] = -(((ge + gw) + gn) + gs) - l1;
-    Y[k] = lT[q];
-    T0[k] = lT[q];
-    acc[k] = 0.f;
   }
 
   // ---- four RK stages (Eq. 18) ----
@@ -269,7 +310,7 @@ __device__ __forceinline__ void energy_rows_tile(
     if (r < 4 || r >= 4 + TY || j >= nT || !lane_out) continue;
     const float Tn = Y[k];
     if (!isfinite(Tn)) err |= ERR_NONFINITE;
-    Tout[(size_t)j * nx + gx] = Tn;
+    st32(Tout, (unsigned)j * (unsigned)nx + gx, Tn);
     const double rc = (double)sh.rcv[w][k][lane];
     v[0] += rc * ((double)Tn - (double)T0[k]);
     v[1] += rc * (double)Tn;

@@ -71,6 +71,18 @@ __device__ __forceinline__ real fast_rcp(real v) {
   else return __builtin_amdgcn_rcpf(v);
 }
 
+// Element i of an array addressed as a uniform base pointer plus a 32-bit byte offset,
+// which maps onto the scalar-base (saddr) form of the global load and store
+// instructions.  One field plane stays below 4 GiB (checked when a context is made).
+template <typename T>
+__device__ __forceinline__ T ld32(const T* __restrict__ base, unsigned i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* __restrict__ base, unsigned i, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)) = v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -156,34 +168,35 @@ template <typename real>
 __device__ __forceinline__ void scatter(real* __restrict__ fs, real* __restrict__ topin, int gx,
                                         int y, int nx, int ny, size_t N, int top_bc,
                                         const real v[9]) {
-  const int xm = wrap1(gx - 1, nx), xp = wrap1(gx + 1, nx);
-  const size_t row = (size_t)y * nx;
-  fs[row + gx] = v[0];
-  fs[N + row + xm] = v[1];
-  fs[3 * N + row + xp] = v[3];
+  const unsigned xm = wrap1(gx - 1, nx), xp = wrap1(gx + 1, nx), x = gx;
+  const unsigned row = (unsigned)y * (unsigned)nx;
+  auto pl = [&](int i) { return fs + (size_t)i * N; };
+  st32(pl(0), row + x, v[0]);
+  st32(pl(1), row + xm, v[1]);
+  st32(pl(3), row + xp, v[3]);
   if (y > 0) {
-    const size_t rb = row - nx;
-    fs[2 * N + rb + gx] = v[2];
-    fs[5 * N + rb + xm] = v[5];
-    fs[6 * N + rb + xp] = v[6];
+    const unsigned rb = row - nx;
+    st32(pl(2), rb + x, v[2]);
+    st32(pl(5), rb + xm, v[5]);
+    st32(pl(6), rb + xp, v[6]);
   } else {
-    fs[4 * N + row + gx] = v[2];
-    fs[7 * N + row + gx] = v[5];
-    fs[8 * N + row + gx] = v[6];
+    st32(pl(4), row + x, v[2]);
+    st32(pl(7), row + x, v[5]);
+    st32(pl(8), row + x, v[6]);
   }
   if (y < ny - 1) {
-    const size_t ra = row + nx;
-    fs[4 * N + ra + gx] = v[4];
-    fs[7 * N + ra + xp] = v[7];
-    fs[8 * N + ra + xm] = v[8];
+    const unsigned ra = row + nx;
+    st32(pl(4), ra + x, v[4]);
+    st32(pl(7), ra + xp, v[7]);
+    st32(pl(8), ra + xm, v[8]);
   } else if (top_bc == TOP_WALL) {
-    fs[2 * N + row + gx] = v[4];
-    fs[5 * N + row + gx] = v[7];
-    fs[6 * N + row + gx] = v[8];
+    st32(pl(2), row + x, v[4]);
+    st32(pl(5), row + x, v[7]);
+    st32(pl(6), row + x, v[8]);
   } else {
-    topin[gx] = v[4];
-    topin[nx + gx] = v[7];
-    topin[2 * nx + gx] = v[8];
+    st32(topin, x, v[4]);
+    st32(topin, nx + x, v[7]);
+    st32(topin, 2 * nx + x, v[8]);
   }
 }
 
@@ -192,20 +205,30 @@ __device__ __forceinline__ void scatter(real* __restrict__ fs, real* __restrict_
 // ---------------------------------------------------------------------------
 // Returns the radicand 2 (p - rho/3) / G (0 when it is not positive); the caller takes
 // the square root in its own precision.
+// The square root and the division use the hardware FP64 estimates refined by Newton
+// steps (relative error near 1e-15, far below the FP32 precision of psi).
 __device__ __forceinline__ double eos_psi2(const KParams& P, double r, double TE, unsigned& err) {
   double phi;
   if (P.flags & FREEZE_EOS_T) {
     phi = P.phi_sat;
   } else {
-    double s = 1.0 + P.kappa * (1.0 - sqrt(TE * P.inv_Tc));
+    const double x = TE * P.inv_Tc;
+    double y = __builtin_amdgcn_rsq(x);   // 1/sqrt(x), then two Newton steps
+    y = y * (1.5 - (0.5 * x) * (y * y));
+    y = y * (1.5 - (0.5 * x) * (y * y));
+    const double s = 1.0 + P.kappa * (1.0 - x * y);
     phi = s * s;
   }
   const double br = P.b * r;
   const double d1 = 1.0 - br;
   const double d2 = 1.0 + 2.0 * br - br * br;
   // p = rho R T / d1 - a phi rho^2 / d2 over one common denominator
-  const double p = (r * P.R * TE * d2 - P.a * phi * r * r * d1) / (d1 * d2);
-  const double rad = 2.0 * (p - r * P.inv3) / P.G;
+  const double den = d1 * d2;
+  double q = __builtin_amdgcn_rcp(den);  // 1/den, then two Newton steps
+  q = fma(q, fma(-den, q, 1.0), q);
+  q = fma(q, fma(-den, q, 1.0), q);
+  const double p = (r * P.R * TE * d2 - P.a * phi * r * r * d1) * q;
+  const double rad = (p - r * P.inv3) * P.two_G;
   if (!(r > 0.0)) err |= ERR_RHO;
   if (!(d1 > 0.0)) err |= ERR_COVOLUME;
   if (!(rad > 0.0)) {
@@ -458,7 +481,7 @@ __global__ void __launch_bounds__(NT)
   __shared__ real spsi[TY + 2][LW];
   __shared__ double red[RED_SIZE];
 
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
 
@@ -978,7 +1001,7 @@ __global__ void __launch_bounds__(NT)
     k_scatter(const KParams P, const real* __restrict__ src, int src_is_rho, real* __restrict__ fdst,
               real* __restrict__ topin, double* __restrict__ partL_out) {
   __shared__ double red[RED_SIZE];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
   const int TY = P.tyL;

@@ -18,7 +18,7 @@ struct KParams {
   int ntxL, ntyL, nblkL, tyL;
   int ntxE, ntyE, nblkE, tyE, txE, pad1;
   // equation of state (FP64)
-  double a, b, R, G, Tc, inv_Tc, kappa, phi_sat, T_sat, inv3;
+  double a, b, R, G, Tc, inv_Tc, kappa, phi_sat, T_sat, inv3, two_G;
   // collision
   double rho_l, rho_v, inv_drho, tau_v, dtau;
   double s_e, s_z, s_q, c_e, c_z, c_q, sig_e, sig_z;
@@ -26,6 +26,9 @@ struct KParams {
   // energy
   double cv, k, cvk, rcw, inv_rcw, lambda_w, T_bottom, T_top, q_bottom;
   double sigma, tau_l, s_e_raw, s_z_raw;
+  // FP32 energy kernel constants: 2k, R/c_v, a kappa^2/(T_c c_v), a kappa (1 + kappa)/(sqrt(T_c) c_v),
+  // kappa^2/T_c, kappa (1 + kappa)/sqrt(T_c)
+  float e_k2, e_g1a, e_g1b, e_g2a, e_kk2, e_kl2;
 };
 
 struct DevDiag {
