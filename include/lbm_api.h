@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 
 enum {
   LBM_OK = 0,
@@ -88,12 +88,18 @@ enum {
  *   Gw0, Gw_top           wall strengths of Eq. 10 at the bottom wall and a top wall
  *   n_sites, site_*       nucleation sites (Sec. 4.2): centre x, width, minimum strength;
  *                         host arrays of n_sites doubles (may be NULL when n_sites = 0)
+ *   tile_rows             rows of temperature grid per energy tile (a performance knob: the
+ *                         fields do not depend on it, the FP64 sums behind the diagnostics
+ *                         do, in their last bits); 0 = automatic (one domain: tiles that fill
+ *                         the device in one round; a batch: the tallest tiles), otherwise
+ *                         clamped to [8, 48]
  */
 typedef struct {
   uint32_t struct_size, abi_version;
   int32_t nx, ny, heater_rows, n_sub;
   int32_t precision, top_bc, bottom_tbc, top_tbc;
   uint32_t flags;
+  int32_t tile_rows;
   double a, b, R, omega, T_sat, G, sigma;
   double tau_l, tau_v, s_e, s_zeta, s_q;
   double rho_l, rho_v;
@@ -189,6 +195,48 @@ int lbm_kernel_times(lbm_ctx *h, double *collide_ms, int64_t *collide_launches,
 
 /* Release the host-side context (the workspace stays the caller's). */
 int lbm_destroy(lbm_ctx *h);
+
+/*
+ * Batches.  n independent domains (sizes, superheats, sites and boundaries may all
+ * differ; precision, n_sub and the LBM_DIFF_ISOTROPIC flag must agree) advance together:
+ * each lbm_batch_step launches one collide kernel and n_sub energy kernels whose
+ * workgroups cover the tiles of every domain, so a batch of small domains fills the
+ * device as one large domain would.  Each domain evolves exactly as it would alone with
+ * the same tile_rows.  The workspace holds a device table of the domains followed by
+ * each domain's own workspace; ownership, streams and errors are as for one domain.
+ * lbm_batch_step has the same graph-capture property as lbm_step.
+ */
+typedef struct lbm_batch lbm_batch;
+
+/* Bytes of device workspace for the batch; 0 if n < 1 or any cfg is invalid. */
+size_t lbm_batch_workspace_bytes(const lbm_config *cfgs, int n);
+
+/* rho0_host[i], T0_host[i]: initial fields of domain i as in lbm_init. */
+int lbm_batch_init(const lbm_config *cfgs, int n, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                   const double *const *rho0_host, const double *const *T0_host, lbm_batch **out);
+int lbm_batch_step(lbm_batch *b, int64_t nsteps);
+int lbm_batch_set_stream(lbm_batch *b, void *hip_stream);
+
+/* Synchronise and fill out[0..n-1]; LBM_ENONFINITE if any domain flagged an error (its
+ * entry says which), after which lbm_batch_step returns LBM_ESTATE. */
+int lbm_batch_observe(lbm_batch *b, lbm_obs *out);
+
+/* Field access of domain i, as lbm_read_field / lbm_write_field. */
+int lbm_batch_read_field(lbm_batch *b, int i, int field, void *dst, size_t bytes, int dst_is_device);
+int lbm_batch_write_field(lbm_batch *b, int i, int field, const void *src, size_t bytes, int src_is_device);
+int lbm_batch_destroy(lbm_batch *b);
+
+/*
+ * Tile-shape autotuner.  For the batch cfgs (n = 1 tunes one domain) it builds the batch
+ * in the caller's workspace (lbm_batch_workspace_bytes bytes) once per candidate energy
+ * tile height, times `steps` steps after `steps` warm-up steps with HIP events on the
+ * stream, and returns the fastest height in *best_rows (pass it as tile_rows) and its
+ * time per step in *best_ms.  Results are cached per process, keyed by the domain sizes,
+ * precision, flags and n_sub; the workspace contents are scratch.  Synchronises.
+ */
+int lbm_autotune_tile_rows(const lbm_config *cfgs, int n, void *d_workspace, size_t ws_bytes,
+                           void *hip_stream, const double *const *rho0_host,
+                           const double *const *T0_host, int steps, int *best_rows, double *best_ms);
 
 /* Static description of a status code. */
 const char *lbm_strerror(int status);

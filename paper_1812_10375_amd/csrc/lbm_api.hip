@@ -8,6 +8,9 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "lbm_api.h"
@@ -35,6 +38,7 @@ bool valid_config(const lbm_config* c) {
   if (c->bottom_tbc != LBM_TBC_DIRICHLET && c->bottom_tbc != LBM_TBC_FLUX) return false;
   if (c->top_tbc != LBM_TBC_DIRICHLET && c->top_tbc != LBM_TBC_ZERO_GRAD) return false;
   if (c->flags & ~15u) return false;
+  if (c->tile_rows < 0) return false;
   if (!(c->a > 0 && c->b > 0 && c->R > 0 && c->T_sat > 0 && c->G < 0)) return false;
   if (!(c->tau_l > 0.5 && c->tau_v > 0.5 && c->s_e > 0 && c->s_e < 2 && c->s_zeta > 0 &&
         c->s_zeta < 2 && c->s_q > 0 && c->s_q < 2))
@@ -73,7 +77,11 @@ Grids grids(const lbm_config* c, int ncu) {
   const int rows_min = (nT + hmax - 1) / hmax;
   const int rows_max = (nT + E_HMIN - 1) / E_HMIN;
   int rows = rows_max;
-  if (ncu > 0) {
+  if (ncu > 0 && c->tile_rows > 0) {
+    // requested tile height, within the kernels' limits
+    const int ty = std::min(std::max(c->tile_rows, E_HMIN), hmax);
+    rows = std::max(rows_min, std::min(rows_max, (nT + ty - 1) / ty));
+  } else if (ncu > 0) {
     const int slots = ncu * (f64 ? E_PER_CU_F64 : E_PER_CU_F32);
     rows = std::max(rows_min, std::min(rows_max, slots / g.ntxE));
   }
@@ -435,6 +443,209 @@ const char* lbm_strerror(int status) {
     case LBM_ESTATE: return "call not allowed in the current state";
     default: return "unknown status";
   }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of independent domains
+// ---------------------------------------------------------------------------
+namespace {
+
+size_t batch_table_bytes(int n) { return align_up((size_t)n * sizeof(lbmk::DomainDev)); }
+
+bool batch_compatible(const lbm_config* cfgs, int n) {
+  if (!cfgs || n < 1) return false;
+  for (int i = 0; i < n; ++i) {
+    if (!valid_config(&cfgs[i])) return false;
+    if (cfgs[i].precision != cfgs[0].precision || cfgs[i].n_sub != cfgs[0].n_sub) return false;
+    if ((cfgs[i].flags ^ cfgs[0].flags) & LBM_DIFF_ISOTROPIC) return false;
+  }
+  return true;
+}
+
+// the tile height a batch uses when the configuration leaves it open
+lbm_config batch_member(const lbm_config& c) {
+  lbm_config m = c;
+  if (m.tile_rows == 0) m.tile_rows = m.precision == LBM_F64 ? E_HMAX : E_HMAX_F32;
+  return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_workspace_bytes(const lbm_config* cfgs, int n) {
+  if (!batch_compatible(cfgs, n)) return 0;
+  size_t total = batch_table_bytes(n);
+  for (int i = 0; i < n; ++i) total += align_up(lbm_workspace_bytes(&cfgs[i]));
+  return total;
+}
+
+int lbm_batch_init(const lbm_config* cfgs, int n, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                   const double* const* rho0_host, const double* const* T0_host, lbm_batch** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  if (!batch_compatible(cfgs, n) || !d_workspace || !rho0_host || !T0_host) return LBM_EINVAL;
+  if (reinterpret_cast<uintptr_t>(d_workspace) & 255) return LBM_EINVAL;
+  const size_t need = lbm_batch_workspace_bytes(cfgs, n);
+  if (ws_bytes < need) return LBM_ENOMEM;
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return LBM_ENOMEM;
+  b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  char* base = reinterpret_cast<char*>(d_workspace);
+  b->table = reinterpret_cast<lbmk::DomainDev*>(base);
+  size_t off = batch_table_bytes(n);
+  std::vector<lbmk::DomainDev> tab(n);
+  int tL = 0, tE = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!rho0_host[i] || !T0_host[i]) {
+      lbm_batch_destroy(b);
+      return LBM_EINVAL;
+    }
+    const lbm_config m = batch_member(cfgs[i]);
+    const size_t bytes = align_up(lbm_workspace_bytes(&m));
+    lbm_ctx* h = nullptr;
+    const int rc = lbm_init(&m, base + off, bytes, hip_stream, rho0_host[i], T0_host[i], &h);
+    if (rc) {
+      lbm_batch_destroy(b);
+      return rc;
+    }
+    b->dom.push_back(h);
+    tab[i].P = h->P;
+    tab[i].L = h->L;
+    tab[i].ws = h->ws;
+    tab[i].tile0L = tL;
+    tab[i].tile0E = tE;
+    tL += h->P.nblkL;
+    tE += h->P.nblkE;
+    off += bytes;
+  }
+  b->nblkL = tL;
+  b->nblkE = tE;
+  if (hipMemcpyAsync(b->table, tab.data(), n * sizeof(lbmk::DomainDev), hipMemcpyHostToDevice, b->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess) {
+    lbm_batch_destroy(b);
+    return LBM_EHIP;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return LBM_EINVAL;
+  for (lbm_ctx* h : b->dom)
+    if (h->bad) return LBM_ESTATE;
+  const bool f64 = b->dom[0]->cfg.precision == LBM_F64;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    if (f64) batch_step_once<double>(b);
+    else batch_step_once<float>(b);
+  }
+  return hip_ok(hipGetLastError());
+}
+
+int lbm_batch_set_stream(lbm_batch* b, void* hip_stream) {
+  if (!b) return LBM_EINVAL;
+  b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  for (lbm_ctx* h : b->dom) h->stream = b->stream;
+  return LBM_OK;
+}
+
+int lbm_batch_observe(lbm_batch* b, lbm_obs* out) {
+  if (!b || !out) return LBM_EINVAL;
+  int status = LBM_OK;
+  // every domain folds its history now, so the shared history slot stays common
+  for (size_t i = 0; i < b->dom.size(); ++i) {
+    const int rc = lbm_observe(b->dom[i], &out[i]);
+    if (rc == LBM_ENONFINITE) status = LBM_ENONFINITE;
+    else if (rc) return rc;
+  }
+  if (status) for (lbm_ctx* h : b->dom) h->bad = true;
+  return status;
+}
+
+int lbm_batch_read_field(lbm_batch* b, int i, int field, void* dst, size_t bytes, int dst_is_device) {
+  if (!b || i < 0 || i >= (int)b->dom.size()) return LBM_EINVAL;
+  return lbm_read_field(b->dom[i], field, dst, bytes, dst_is_device);
+}
+
+int lbm_batch_write_field(lbm_batch* b, int i, int field, const void* src, size_t bytes, int src_is_device) {
+  if (!b || i < 0 || i >= (int)b->dom.size()) return LBM_EINVAL;
+  if (b->dom[i]->hist_count != 0) return LBM_ESTATE;  // call lbm_batch_observe first
+  return lbm_write_field(b->dom[i], field, src, bytes, src_is_device);
+}
+
+int lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_EINVAL;
+  for (lbm_ctx* h : b->dom) lbm_destroy(h);
+  delete b;
+  return LBM_OK;
+}
+
+int lbm_autotune_tile_rows(const lbm_config* cfgs, int n, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                           const double* const* rho0_host, const double* const* T0_host, int steps,
+                           int* best_rows, double* best_ms) {
+  static std::mutex mu;
+  static std::map<std::string, std::pair<int, double>> cache;
+  if (!best_rows || !best_ms || steps < 1 || !batch_compatible(cfgs, n)) return LBM_EINVAL;
+  if (ws_bytes < lbm_batch_workspace_bytes(cfgs, n)) return LBM_ENOMEM;
+  std::string key = std::to_string(cfgs[0].precision) + "/" + std::to_string(cfgs[0].n_sub) + "/" +
+                    std::to_string(cfgs[0].flags & LBM_DIFF_ISOTROPIC);
+  for (int i = 0; i < n; ++i)
+    key += "/" + std::to_string(cfgs[i].nx) + "x" + std::to_string(cfgs[i].ny) + "+" +
+           std::to_string(cfgs[i].heater_rows);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      *best_rows = it->second.first;
+      *best_ms = it->second.second;
+      return LBM_OK;
+    }
+  }
+  const int hmax = cfgs[0].precision == LBM_F64 ? E_HMAX : E_HMAX_F32;
+  const int cand[] = {8, 12, 16, 20, 24, 32, 40, hmax};
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return LBM_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return LBM_EHIP;
+  }
+  std::vector<lbm_config> cs(cfgs, cfgs + n);
+  int best = 0;
+  double bms = 0.0;
+  int rc = LBM_OK;
+  for (int r : cand) {
+    for (auto& c : cs) c.tile_rows = r;
+    lbm_batch* b = nullptr;
+    rc = lbm_batch_init(cs.data(), n, d_workspace, ws_bytes, hip_stream, rho0_host, T0_host, &b);
+    if (rc) break;
+    float ms = 0.f;
+    rc = lbm_batch_step(b, steps);
+    if (!rc && (hipEventRecord(e0, st) != hipSuccess || (rc = lbm_batch_step(b, steps)) != 0 ||
+                hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = rc ? rc : LBM_EHIP;
+    lbm_batch_destroy(b);
+    if (rc) break;
+    const double per = (double)ms / steps;
+    if (best == 0 || per < bms) {
+      best = r;
+      bms = per;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = {best, bms};
+  }
+  *best_rows = best;
+  *best_ms = bms;
+  return LBM_OK;
 }
 
 }  // extern "C"

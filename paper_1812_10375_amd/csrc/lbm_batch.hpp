@@ -1,0 +1,89 @@
+// lbm_batch.hpp -- batched step over independent domains.  One launch covers the tiles
+// of every domain of a batch: a workgroup takes global tile g (XCD-aware order), finds
+// its domain in the device table by binary search over the first-tile offsets, and runs
+// the same per-tile code as the single-domain kernels with that domain's parameters and
+// buffers.  All domains share the step parity, so every argument of a launch depends
+// only on the parity and the diagnostics history slot.
+#pragma once
+#include "lbm_energy_f32.hpp"
+#include "lbm_kernels.hpp"
+
+namespace lbmk {
+
+// Largest d with first(d) <= g (first(0) = 0, increasing).
+template <bool ENERGY>
+__device__ __forceinline__ int batch_domain(const DomainDev* __restrict__ tab, int ndom, int g) {
+  int lo = 0, hi = ndom - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int first = ENERGY ? tab[mid].tile0E : tab[mid].tile0L;
+    if (first <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename real, int TY>
+__global__ void __launch_bounds__(NT)
+    k_collide_batch(const DomainDev* __restrict__ tab, int ndom, int fcur, int tcur, int cur) {
+  const int g = xcd_tile(blockIdx.x, gridDim.x);
+  const int d = batch_domain<false>(tab, ndom, g);
+  const DomainDev& D = tab[d];
+  const Layout& L = D.L;
+  char* ws = D.ws;
+  const int prev = 1 - cur;
+  collide_tile<real, TY>(
+      D.P, reinterpret_cast<const real*>(ws + L.f[fcur]), reinterpret_cast<real*>(ws + L.f[1 - fcur]),
+      reinterpret_cast<const real*>(ws + L.topin), reinterpret_cast<const real*>(ws + L.T[tcur]),
+      reinterpret_cast<const real*>(ws + L.gw), reinterpret_cast<real*>(ws + L.rho),
+      reinterpret_cast<real*>(ws + L.ux), reinterpret_cast<real*>(ws + L.uy),
+      reinterpret_cast<const double*>(ws + L.mstate[prev]), reinterpret_cast<const double*>(ws + L.pmin[prev]),
+      reinterpret_cast<double*>(ws + L.mstate[cur]), reinterpret_cast<double*>(ws + L.partL[cur]),
+      reinterpret_cast<DevDiag*>(ws + L.diag), reinterpret_cast<const long long*>(ws + L.dstep[prev]),
+      reinterpret_cast<long long*>(ws + L.dstep[cur]), g - D.tile0L);
+}
+
+// Energy update of every domain (FP32 register-row kernel).  fcur names the buffer that
+// holds the populations after this step's collision (read by the open-top rule).
+template <int NW, int B, int WPE>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
+    k_energy_rows_batch(const DomainDev* __restrict__ tab, int ndom, int fpost, int tcur, int cur,
+                        int hslot, int sub, double dtd) {
+  const int g = xcd_tile(blockIdx.x, gridDim.x);
+  const int d = batch_domain<true>(tab, ndom, g);
+  const DomainDev& D = tab[d];
+  const Layout& L = D.L;
+  char* ws = D.ws;
+  energy_rows_step<NW, B>(
+      D.P, reinterpret_cast<const float*>(ws + L.T[tcur]), reinterpret_cast<float*>(ws + L.T[1 - tcur]),
+      reinterpret_cast<const float*>(ws + L.rho), reinterpret_cast<const float*>(ws + L.ux),
+      reinterpret_cast<const float*>(ws + L.uy),
+      reinterpret_cast<double*>(ws + L.hist) + (size_t)hslot * D.P.nblkE * 5,
+      reinterpret_cast<const float*>(ws + L.f[fpost]), reinterpret_cast<float*>(ws + L.topin),
+      reinterpret_cast<const double*>(ws + L.partL[cur]), reinterpret_cast<double*>(ws + L.pmin[cur]),
+      reinterpret_cast<DevDiag*>(ws + L.diag), sub, dtd,
+      reinterpret_cast<const long long*>(ws + L.dstep[1 - cur]), g - D.tile0E);
+}
+
+// Energy update of every domain (LDS kernel: FP64, or the isotropic scheme).
+template <typename real, bool ISO, int NW, int HMAX>
+__global__ void __launch_bounds__(NW * 64)
+    k_energy_batch(const DomainDev* __restrict__ tab, int ndom, int fpost, int tcur, int cur, int hslot,
+                   int sub, double dtd) {
+  const int g = xcd_tile(blockIdx.x, gridDim.x);
+  const int d = batch_domain<true>(tab, ndom, g);
+  const DomainDev& D = tab[d];
+  const Layout& L = D.L;
+  char* ws = D.ws;
+  energy_lds_tile<real, ISO, NW, HMAX>(
+      D.P, reinterpret_cast<const real*>(ws + L.T[tcur]), reinterpret_cast<real*>(ws + L.T[1 - tcur]),
+      reinterpret_cast<const real*>(ws + L.rho), reinterpret_cast<const real*>(ws + L.ux),
+      reinterpret_cast<const real*>(ws + L.uy),
+      reinterpret_cast<double*>(ws + L.hist) + (size_t)hslot * D.P.nblkE * 5,
+      reinterpret_cast<const real*>(ws + L.f[fpost]), reinterpret_cast<real*>(ws + L.topin),
+      reinterpret_cast<const double*>(ws + L.partL[cur]), reinterpret_cast<double*>(ws + L.pmin[cur]),
+      reinterpret_cast<DevDiag*>(ws + L.diag), sub, dtd,
+      reinterpret_cast<const long long*>(ws + L.dstep[1 - cur]), g - D.tile0E);
+}
+
+}  // namespace lbmk

@@ -29,10 +29,7 @@ constexpr int E_PER_CU_F32 = 2, E_PER_CU_F64 = 1;
 // Steps of energy partials kept before they are folded into the diagnostics.
 constexpr int HIST = LBM_HISTORY_STEPS;
 
-// Byte offsets of the arrays carved out of the caller's workspace.
-struct Layout {
-  size_t f[2], T[2], rho, ux, uy, topin, gw, partL[2], pmin[2], mstate[2], dstep[2], hist, steps, diag, total;
-};
+using lbmk::Layout;
 
 }  // namespace lbmh
 
@@ -59,6 +56,13 @@ struct lbm_ctx {
   }
 };
 
+struct lbm_batch {
+  std::vector<lbm_ctx*> dom;  // per-domain contexts; the batch keeps their bookkeeping in step
+  hipStream_t stream;
+  lbmk::DomainDev* table;     // device table, first in the workspace
+  int nblkL, nblkE;           // collide and energy tiles over all domains
+};
+
 namespace lbmh {
 // Event pair around one launch when timing is on: begin returns the start event's
 // index (or -1), end records the stop event.
@@ -71,4 +75,5 @@ template <typename T> void finish_reductions(lbm_ctx* h);  // fold all pending s
 template <typename T> void gather_populations(lbm_ctx* h, T* out);
 template <typename T> int init_fields(lbm_ctx* h, const double* rho0, const double* T0,
                                       const double* gw);
+template <typename T> void batch_step_once(lbm_batch* b);
 }  // namespace lbmh

@@ -337,18 +337,15 @@ __device__ __forceinline__ void energy_rows_tile(
   }
 }
 
-template <int NW, int B, int WPE>
-__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
-    k_energy_rows(const KParams P, const float* __restrict__ Tin, float* __restrict__ Tout,
-                  const float* __restrict__ rho, const float* __restrict__ uxa,
-                  const float* __restrict__ uya, double* __restrict__ hist_slot,
-                  const float* __restrict__ fpost, float* __restrict__ topin,
-                  const double* __restrict__ partL_cur, double* __restrict__ pmin_cur,
-                  DevDiag* __restrict__ diag, int sub, double dtd,
-                  const long long* __restrict__ dstep_prev) {
+template <int NW, int B>
+__device__ __forceinline__ void energy_rows_step(
+    const KParams& P, const float* __restrict__ Tin, float* __restrict__ Tout,
+    const float* __restrict__ rho, const float* __restrict__ uxa, const float* __restrict__ uya,
+    double* __restrict__ hist_slot, const float* __restrict__ fpost, float* __restrict__ topin,
+    const double* __restrict__ partL_cur, double* __restrict__ pmin_cur, DevDiag* __restrict__ diag,
+    int sub, double dtd, const long long* __restrict__ dstep_prev, int tile) {
   __shared__ RowsShared<NW, B> sh;
   const int nT = P.nT, TY = P.tyE;
-  const int tile = xcd_tile(blockIdx.x, P.nblkE);
   const int x0 = (tile % P.ntxE) * P.txE, j0 = (tile / P.ntxE) * TY;
   const bool plain_tile = (j0 - 4 >= P.nh) && (j0 + TY + 3 <= nT - 1);
   if (plain_tile)
@@ -380,6 +377,19 @@ __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WP
     block_sum_n<1, NW>(ms, sh.red);
     if (t == 0) pmin_cur[tile % P.ntxE] = ms[0];
   }
+}
+
+template <int NW, int B, int WPE>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
+    k_energy_rows(const KParams P, const float* __restrict__ Tin, float* __restrict__ Tout,
+                  const float* __restrict__ rho, const float* __restrict__ uxa,
+                  const float* __restrict__ uya, double* __restrict__ hist_slot,
+                  const float* __restrict__ fpost, float* __restrict__ topin,
+                  const double* __restrict__ partL_cur, double* __restrict__ pmin_cur,
+                  DevDiag* __restrict__ diag, int sub, double dtd,
+                  const long long* __restrict__ dstep_prev) {
+  energy_rows_step<NW, B>(P, Tin, Tout, rho, uxa, uya, hist_slot, fpost, topin, partL_cur, pmin_cur, diag, sub,
+                          dtd, dstep_prev, xcd_tile(blockIdx.x, P.nblkE));
 }
 
 }  // namespace lbmk

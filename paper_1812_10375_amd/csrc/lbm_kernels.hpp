@@ -468,14 +468,13 @@ __device__ __forceinline__ double outlet_column(const KParams& P, int x, real U,
 //            write f*^n, rho, u; FP64 partial of the mass that the next pull sees.
 // ---------------------------------------------------------------------------
 template <typename real, int TY>
-__global__ void __launch_bounds__(NT)
-    k_collide(const KParams P, const real* __restrict__ fsrc, real* __restrict__ fdst,
-              const real* __restrict__ topin, const real* __restrict__ Tcur,
-              const real* __restrict__ gw, real* __restrict__ rho_out, real* __restrict__ ux_out,
-              real* __restrict__ uy_out, const double* __restrict__ mstate_prev,
-              const double* __restrict__ pmin_prev, double* __restrict__ mstate_cur,
-              double* __restrict__ partL_out, DevDiag* __restrict__ diag,
-              const long long* __restrict__ dstep_prev, long long* __restrict__ dstep_cur) {
+__device__ __forceinline__ void collide_tile(
+    const KParams& P, const real* __restrict__ fsrc, real* __restrict__ fdst,
+    const real* __restrict__ topin, const real* __restrict__ Tcur, const real* __restrict__ gw,
+    real* __restrict__ rho_out, real* __restrict__ ux_out, real* __restrict__ uy_out,
+    const double* __restrict__ mstate_prev, const double* __restrict__ pmin_prev,
+    double* __restrict__ mstate_cur, double* __restrict__ partL_out, DevDiag* __restrict__ diag,
+    const long long* __restrict__ dstep_prev, long long* __restrict__ dstep_cur, int tile) {
   constexpr int RPT = TY / 4;  // rows per thread
   constexpr int LW = 66;
   __shared__ real spsi[TY + 2][LW];
@@ -494,7 +493,6 @@ __global__ void __launch_bounds__(NT)
     for (int b = 0; b < P.ntxE; ++b) mnow += pmin_prev[b];
   }
 
-  const int tile = xcd_tile(blockIdx.x, P.nblkL);
   const int x0 = (tile % P.ntxL) * 64, y0 = (tile / P.ntxL) * TY;
   unsigned err = 0;
 
@@ -543,7 +541,7 @@ __global__ void __launch_bounds__(NT)
   const long long step = dstep_prev[0];
   if (t == 0) {
     red[112] = mnow;
-    if (blockIdx.x == 0) {
+    if (tile == 0) {
       mstate_cur[0] = mnow;
       dstep_cur[0] = step + 1;
     }
@@ -637,6 +635,19 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
+template <typename real, int TY>
+__global__ void __launch_bounds__(NT)
+    k_collide(const KParams P, const real* __restrict__ fsrc, real* __restrict__ fdst,
+              const real* __restrict__ topin, const real* __restrict__ Tcur,
+              const real* __restrict__ gw, real* __restrict__ rho_out, real* __restrict__ ux_out,
+              real* __restrict__ uy_out, const double* __restrict__ mstate_prev,
+              const double* __restrict__ pmin_prev, double* __restrict__ mstate_cur,
+              double* __restrict__ partL_out, DevDiag* __restrict__ diag,
+              const long long* __restrict__ dstep_prev, long long* __restrict__ dstep_cur) {
+  collide_tile<real, TY>(P, fsrc, fdst, topin, Tcur, gw, rho_out, ux_out, uy_out, mstate_prev, pmin_prev,
+                         mstate_cur, partL_out, diag, dstep_prev, dstep_cur, xcd_tile(blockIdx.x, P.nblkL));
+}
+
 // ---------------------------------------------------------------------------
 // Energy kernel: T^n -> T^{n+1} on a tile of the temperature grid (heater and fluid
 // rows), rho^n and u^n frozen (Eq. 17-18, Eq. 22-27).
@@ -652,14 +663,12 @@ __global__ void __launch_bounds__(NT)
 constexpr int EW = 64;  // LDS row length = wavefront size
 
 template <typename real, bool ISO, int NW, int HMAX>
-__global__ void __launch_bounds__(NW * 64)
-    k_energy(const KParams P, const real* __restrict__ Tin, real* __restrict__ Tout,
-             const real* __restrict__ rho, const real* __restrict__ uxa,
-             const real* __restrict__ uya, double* __restrict__ hist_slot,
-             const real* __restrict__ fpost, real* __restrict__ topin,
-             const double* __restrict__ partL_cur, double* __restrict__ pmin_cur,
-             DevDiag* __restrict__ diag, int sub, double dtd,
-             const long long* __restrict__ dstep_prev) {
+__device__ __forceinline__ void energy_lds_tile(
+    const KParams& P, const real* __restrict__ Tin, real* __restrict__ Tout,
+    const real* __restrict__ rho, const real* __restrict__ uxa, const real* __restrict__ uya,
+    double* __restrict__ hist_slot, const real* __restrict__ fpost, real* __restrict__ topin,
+    const double* __restrict__ partL_cur, double* __restrict__ pmin_cur, DevDiag* __restrict__ diag,
+    int sub, double dtd, const long long* __restrict__ dstep_prev, int tile) {
   constexpr int H4M = HMAX + 8;
   constexpr int NR4 = (H4M + NW - 1) / NW;        // LDS rows per wave (load, faces)
   constexpr int NC = (HMAX + 6 + NW - 1) / NW;    // stage-1 rows per wave
@@ -673,7 +682,6 @@ __global__ void __launch_bounds__(NW * 64)
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nx = P.nx, nT = P.nT, nh = P.nh;
   const int TXr = P.txE, TY = P.tyE, H4 = TY + 8;
-  const int tile = xcd_tile(blockIdx.x, P.nblkE);
   const int x0 = (tile % P.ntxE) * TXr, j0 = (tile / P.ntxE) * TY;
   const int gx = wrapm(x0 - 4 + lane, nx);  // global column of this lane
   const bool top_open = P.top_bc != TOP_WALL;
@@ -991,6 +999,19 @@ __global__ void __launch_bounds__(NW * 64)
     block_sum_n<1, NW>(ms, red);
     if (t == 0) pmin_cur[tile % P.ntxE] = ms[0];
   }
+}
+
+template <typename real, bool ISO, int NW, int HMAX>
+__global__ void __launch_bounds__(NW * 64)
+    k_energy(const KParams P, const real* __restrict__ Tin, real* __restrict__ Tout,
+             const real* __restrict__ rho, const real* __restrict__ uxa,
+             const real* __restrict__ uya, double* __restrict__ hist_slot,
+             const real* __restrict__ fpost, real* __restrict__ topin,
+             const double* __restrict__ partL_cur, double* __restrict__ pmin_cur,
+             DevDiag* __restrict__ diag, int sub, double dtd,
+             const long long* __restrict__ dstep_prev) {
+  energy_lds_tile<real, ISO, NW, HMAX>(P, Tin, Tout, rho, uxa, uya, hist_slot, fpost, topin, partL_cur,
+                                       pmin_cur, diag, sub, dtd, dstep_prev, xcd_tile(blockIdx.x, P.nblkE));
 }
 
 // ---------------------------------------------------------------------------

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "lbm_batch.hpp"
 #include "lbm_ctx.hpp"
 #include "lbm_energy_f32.hpp"
 #include "lbm_kernels.hpp"
@@ -84,6 +85,42 @@ void step_once(lbm_ctx* h) {
   if (h->hist_count == HIST) finish_reductions<real>(h);
 }
 
+// One step of every domain of a batch: the batched collide kernel, then the batched
+// energy kernel once per energy sub-step.  All domains share the parity, the buffer
+// indices and the history slot; the per-domain host bookkeeping advances together.
+template <typename real>
+void batch_step_once(lbm_batch* b) {
+  lbm_ctx* h0 = b->dom[0];
+  constexpr bool f64 = sizeof(real) == 8;
+  const int n = (int)b->dom.size();
+  const int cur = (int)(h0->step & 1), fcur = h0->fcur;
+  int tcur = h0->tcur;
+  const int hslot = (h0->hist_first + h0->hist_count) % HIST;
+  const bool iso = (h0->cfg.flags & LBM_DIFF_ISOTROPIC) != 0;
+  hipLaunchKernelGGL((lbmk::k_collide_batch<real, f64 ? TY_F64 : TY_F32>), dim3(b->nblkL), dim3(NT), 0,
+                     b->stream, b->table, n, fcur, tcur, cur);
+  const double dt = 1.0 / h0->cfg.n_sub;
+  for (int sub = 0; sub < h0->cfg.n_sub; ++sub) {
+    if (iso)
+      hipLaunchKernelGGL((lbmk::k_energy_batch<real, true, E_NW, E_HMAX>), dim3(b->nblkE), dim3(E_NW * 64), 0,
+                         b->stream, b->table, n, 1 - fcur, tcur, cur, hslot, sub, dt);
+    else if constexpr (f64)
+      hipLaunchKernelGGL((lbmk::k_energy_batch<real, false, E_NW, E_HMAX>), dim3(b->nblkE), dim3(E_NW * 64), 0,
+                         b->stream, b->table, n, 1 - fcur, tcur, cur, hslot, sub, dt);
+    else
+      hipLaunchKernelGGL((lbmk::k_energy_rows_batch<E_RNW, E_BAND, E_RWPE>), dim3(b->nblkE), dim3(E_RNW * 64), 0,
+                         b->stream, b->table, n, 1 - fcur, tcur, cur, hslot, sub, dt);
+    tcur = 1 - tcur;
+  }
+  for (lbm_ctx* h : b->dom) {
+    h->tcur = tcur;
+    h->hist_count += 1;
+    h->fcur = 1 - fcur;
+    h->step += 1;
+    if (h->hist_count == HIST) finish_reductions<real>(h);
+  }
+}
+
 // Store pre-collision populations (or the equilibrium at rest of a density field)
 // as the current state; its mass partials go where the next collide kernel reads them.
 template <typename real>
@@ -158,4 +195,5 @@ int init_fields(lbm_ctx* h, const double* rho0, const double* T0, const double* 
   template void finish_reductions<T>(lbm_ctx*);                                             \
   template void gather_populations<T>(lbm_ctx*, T*);                                        \
   template int init_fields<T>(lbm_ctx*, const double*, const double*, const double*);       \
+  template void batch_step_once<T>(lbm_batch*);                                             \
   }

@@ -40,4 +40,18 @@ struct DevDiag {
   unsigned long long first_bad;
 };
 
+// Byte offsets of the arrays carved out of a domain's workspace.
+struct Layout {
+  size_t f[2], T[2], rho, ux, uy, topin, gw, partL[2], pmin[2], mstate[2], dstep[2], hist, steps, diag, total;
+};
+
+// One domain of a batch, as the batched kernels see it (device memory).  tile0L and
+// tile0E are the domain's first tile in the batch's collide and energy grids.
+struct DomainDev {
+  KParams P;
+  Layout L;
+  char* ws;
+  int tile0L, tile0E;
+};
+
 }  // namespace lbmk

@@ -19,14 +19,14 @@ FLAG_BITS = {"freeze_eos_T": 1, "no_advection": 2, "no_latent": 4, "diff_isotrop
 FIELDS = {"f": 0, "rho": 1, "ux": 2, "uy": 3, "T": 4, "Gw": 10}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
           -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class LbmConfig(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("abi_version", C.c_uint32),
                 ("nx", C.c_int32), ("ny", C.c_int32), ("heater_rows", C.c_int32), ("n_sub", C.c_int32),
                 ("precision", C.c_int32), ("top_bc", C.c_int32), ("bottom_tbc", C.c_int32),
-                ("top_tbc", C.c_int32), ("flags", C.c_uint32)] + [
+                ("top_tbc", C.c_int32), ("flags", C.c_uint32), ("tile_rows", C.c_int32)] + [
         (n, C.c_double) for n in (
             "a", "b", "R", "omega", "T_sat", "G", "sigma", "tau_l", "tau_v", "s_e", "s_zeta", "s_q",
             "rho_l", "rho_v", "cv", "k", "rho_w", "cv_w", "lambda_w", "g", "T_bottom", "T_top",
@@ -85,6 +85,27 @@ def library():
                                        C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.lbm_strerror.restype = C.c_char_p
         L.lbm_strerror.argtypes = [C.c_int]
+        bp = C.c_void_p
+        dpp = C.POINTER(C.POINTER(C.c_double))
+        L.lbm_batch_workspace_bytes.restype = C.c_size_t
+        L.lbm_batch_workspace_bytes.argtypes = [cfgp, C.c_int]
+        L.lbm_batch_init.restype = C.c_int
+        L.lbm_batch_init.argtypes = [cfgp, C.c_int, vp, C.c_size_t, vp, dpp, dpp, C.POINTER(bp)]
+        L.lbm_batch_step.restype = C.c_int
+        L.lbm_batch_step.argtypes = [bp, C.c_int64]
+        L.lbm_batch_set_stream.restype = C.c_int
+        L.lbm_batch_set_stream.argtypes = [bp, vp]
+        L.lbm_batch_observe.restype = C.c_int
+        L.lbm_batch_observe.argtypes = [bp, C.POINTER(LbmObs)]
+        L.lbm_batch_read_field.restype = C.c_int
+        L.lbm_batch_read_field.argtypes = [bp, C.c_int, C.c_int, vp, C.c_size_t, C.c_int]
+        L.lbm_batch_write_field.restype = C.c_int
+        L.lbm_batch_write_field.argtypes = [bp, C.c_int, C.c_int, vp, C.c_size_t, C.c_int]
+        L.lbm_batch_destroy.restype = C.c_int
+        L.lbm_batch_destroy.argtypes = [bp]
+        L.lbm_autotune_tile_rows.restype = C.c_int
+        L.lbm_autotune_tile_rows.argtypes = [cfgp, C.c_int, vp, C.c_size_t, vp, dpp, dpp, C.c_int,
+                                             C.POINTER(C.c_int), C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -105,6 +126,7 @@ def make_config(sc):
     c.bottom_tbc = TBC[sc["bottom_tbc"]]
     c.top_tbc = TBC[sc["top_tbc"]]
     c.flags = sum(FLAG_BITS[f] for f in sc.get("flags", ()))
+    c.tile_rows = int(sc.get("tile_rows", 0))
     for n in ("a", "b", "R", "omega", "T_sat", "G", "sigma", "tau_l", "tau_v", "s_e", "s_zeta",
               "s_q", "rho_l", "rho_v", "cv", "k", "rho_w", "cv_w", "lambda_w", "g", "T_bottom",
               "T_top", "q_bottom", "Gw0", "Gw_top"):
@@ -216,3 +238,134 @@ class Lattice:
                                        arr.nbytes, 0)
         if rc != 0:
             raise LbmError(rc, "lbm_write_field")
+
+
+def _shape_of(sc, name):
+    nx, ny, nh = sc["nx"], sc["ny"], sc["heater_rows"]
+    return {"f": (9, ny, nx), "T": (nh + ny, nx), "Gw": (nx,)}.get(name, (ny, nx))
+
+
+class _BatchInputs:
+    """Marshalled configurations and initial fields of a list of scenarios."""
+
+    def __init__(self, scs):
+        n = len(scs)
+        self.n = n
+        self.cfgs = (LbmConfig * n)()
+        self.keep = []
+        self.fields = []
+        for i, sc in enumerate(scs):
+            c, keep = make_config(sc)
+            self.cfgs[i] = c
+            self.keep.append(keep)
+            nx, ny, nh = sc["nx"], sc["ny"], sc["heater_rows"]
+            rho0 = np.ascontiguousarray(sc["rho0"], dtype=np.float64)
+            T0 = np.ascontiguousarray(sc["T0"], dtype=np.float64)
+            if rho0.shape != (ny, nx) or T0.shape != (nh + ny, nx):
+                raise ValueError("initial field shapes do not match the lattice of domain %d" % i)
+            self.fields.append((rho0, T0))
+        DP = C.POINTER(C.c_double)
+        self.rho0 = (DP * n)(*[_dptr(r) for r, _ in self.fields])
+        self.T0 = (DP * n)(*[_dptr(t) for _, t in self.fields])
+
+    def workspace_bytes(self):
+        return library().lbm_batch_workspace_bytes(self.cfgs, self.n)
+
+
+class BatchLattice:
+    """Independent domains advanced together by the batched kernels (one collide and
+    n_sub energy launches per step for the whole batch)."""
+
+    def __init__(self, scs, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the hybrid LB library needs a GPU")
+        L = library()
+        self.scs = list(scs)
+        self.inp = _BatchInputs(self.scs)
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        nbytes = self.inp.workspace_bytes()
+        if nbytes == 0:
+            raise LbmError(-1, "lbm_batch_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        self.dtype = np.float64 if self.inp.cfgs[0].precision == F64 else np.float32
+        h = C.c_void_p()
+        rc = L.lbm_batch_init(self.inp.cfgs, self.inp.n, C.c_void_p(self.ws.data_ptr()), nbytes,
+                              C.c_void_p(self.stream.cuda_stream), self.inp.rho0, self.inp.T0, C.byref(h))
+        if rc != 0:
+            raise LbmError(rc, "lbm_batch_init")
+        self.h = h
+
+    def __len__(self):
+        return self.inp.n
+
+    def close(self):
+        if getattr(self, "h", None):
+            library().lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        rc = library().lbm_batch_step(self.h, int(n))
+        if rc != 0:
+            raise LbmError(rc, "lbm_batch_step")
+
+    def set_stream(self, stream):
+        rc = library().lbm_batch_set_stream(self.h, C.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise LbmError(rc, "lbm_batch_set_stream")
+        self.stream = stream
+
+    def observe(self, check=True):
+        """List of per-domain observation dictionaries."""
+        obs = (LbmObs * self.inp.n)()
+        rc = library().lbm_batch_observe(self.h, obs)
+        if check and rc != 0:
+            raise LbmError(rc, "lbm_batch_observe")
+        out = []
+        for o in obs:
+            d = {k: getattr(o, k) for k, _ in LbmObs._fields_}
+            d["status"] = rc
+            out.append(d)
+        return out
+
+    def read(self, i, name):
+        out = np.empty(_shape_of(self.scs[i], name), dtype=self.dtype)
+        rc = library().lbm_batch_read_field(self.h, int(i), FIELDS[name], out.ctypes.data_as(C.c_void_p),
+                                            out.nbytes, 0)
+        if rc != 0:
+            raise LbmError(rc, "lbm_batch_read_field")
+        return out.astype(np.float64)
+
+    def write(self, i, name, values):
+        arr = np.ascontiguousarray(np.asarray(values).reshape(_shape_of(self.scs[i], name)), dtype=self.dtype)
+        rc = library().lbm_batch_write_field(self.h, int(i), FIELDS[name], arr.ctypes.data_as(C.c_void_p),
+                                             arr.nbytes, 0)
+        if rc != 0:
+            raise LbmError(rc, "lbm_batch_write_field")
+
+
+def autotune_tile_rows(scs, steps=20, device=None, stream=None):
+    """Fastest energy tile height for this batch of scenarios (cached per process by the
+    library): returns (tile_rows, ms per step)."""
+    import torch
+    inp = _BatchInputs(scs)
+    nbytes = inp.workspace_bytes()
+    if nbytes == 0:
+        raise LbmError(-1, "lbm_batch_workspace_bytes")
+    dev = torch.device("cuda") if device is None else torch.device(device)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream(dev) if stream is None else stream
+    rows, ms = C.c_int(), C.c_double()
+    rc = library().lbm_autotune_tile_rows(inp.cfgs, inp.n, C.c_void_p(ws.data_ptr()), nbytes,
+                                          C.c_void_p(st.cuda_stream), inp.rho0, inp.T0, int(steps),
+                                          C.byref(rows), C.byref(ms))
+    if rc != 0:
+        raise LbmError(rc, "lbm_autotune_tile_rows")
+    return rows.value, ms.value

@@ -86,3 +86,19 @@ def test_product_package_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", text, re.M), fn
                 assert "liboracle" not in text and "lbm_oracle" not in text, fn
+
+
+def test_batch_rejects_incompatible_domains():
+    L = lbm.library()
+    a = S.film_evaporation(nx=16, ny=16, film=4, precision="f32")
+    b = S.film_evaporation(nx=24, ny=12, film=4, precision="f32")
+    good = lbm._BatchInputs([a, b])
+    assert L.lbm_batch_workspace_bytes(good.cfgs, 2) >= (lbm.workspace_bytes(a) + lbm.workspace_bytes(b))
+    for change in ({"precision": "f64"}, {"n_sub": 2}, {"flags": ("diff_isotropic",)}, {"tile_rows": -1}):
+        bad = lbm._BatchInputs([a, dict(b, **change)])
+        assert L.lbm_batch_workspace_bytes(bad.cfgs, 2) == 0, change
+        h = C.c_void_p()
+        fake = C.c_void_p(1 << 20)  # never dereferenced: the call fails before any device work
+        rc = L.lbm_batch_init(bad.cfgs, 2, fake, 1 << 30, None, bad.rho0, bad.T0, C.byref(h))
+        assert rc == -1 and not h.value, change
+    assert L.lbm_batch_workspace_bytes(good.cfgs, 0) == 0

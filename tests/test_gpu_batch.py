@@ -1,0 +1,107 @@
+"""Batched step over independent domains: each domain of a batch must evolve exactly as
+it does alone (same tile height), in FP64 and in FP32; batches replay from HIP graphs;
+the tile-shape autotuner returns one of its candidates and caches it."""
+import numpy as np
+import pytest
+
+from paper_1812_10375_amd import scenarios as S
+from parity import log
+
+pytestmark = pytest.mark.gpu
+
+HIST = 256
+
+
+def _mixed(prec, rows=16):
+    """Domains of uneven sizes, superheats, sites and boundaries."""
+    scs = [
+        S.pool_boiling(nx=96, ny=64, heater_rows=5, n_sites=2, min_spacing=16, seed=21, precision=prec,
+                       superheat=0.08),
+        S.film_evaporation(nx=70, ny=50, film=12, superheat=0.05, seed=22, precision=prec),
+        S.pool_boiling(nx=130, ny=40, heater_rows=3, n_sites=1, min_spacing=8, seed=23, precision=prec,
+                       superheat=0.15),
+        S.interface_conduction(nx=8, ny=96, exact_energy=False, steps=10),
+    ]
+    scs[3]["precision"] = prec
+    for sc in scs:
+        sc["tile_rows"] = rows
+    return scs
+
+
+def _fields(read):
+    return {k: read(k) for k in ("f", "rho", "ux", "uy", "T")}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_domains_evolve_as_they_do_alone(prec):
+    from paper_1812_10375_amd.lbm import BatchLattice, Lattice
+    scs = _mixed(prec)
+    steps = 300
+    log("[batch] %d domains %s %d steps" % (len(scs), prec, steps))
+    bat = BatchLattice(scs)
+    bat.step(steps)
+    bobs = bat.observe()
+    for i, sc in enumerate(scs):
+        one = Lattice(sc)
+        one.step(steps)
+        oobs = one.observe()
+        a = _fields(lambda k: bat.read(i, k))
+        b = _fields(one.read)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (i, k, np.abs(a[k] - b[k]).max())
+        for k in ("mass", "energy", "Q_bottom_cum", "dE_cum", "q_bottom_mean", "max_speed"):
+            assert bobs[i][k] == oobs[k], (i, k)
+        assert bobs[i]["step"] == steps
+        one.close()
+
+
+def test_batch_domain_against_the_oracle():
+    from oracle.lbm import OracleSim
+    from paper_1812_10375_amd.lbm import BatchLattice
+    scs = _mixed("f64")
+    bat = BatchLattice(scs)
+    bat.step(100)
+    bat.observe()
+    for i in (0, 2):
+        orc = OracleSim(scs[i])
+        assert orc.step(100) == 0
+        for k in ("rho", "T"):
+            g, o = bat.read(i, k), orc.field(k)
+            assert np.abs(g - o).max() / np.abs(o).max() < 1e-12, (i, k)
+
+
+def test_batch_graph_replay_matches_eager():
+    import torch
+    from paper_1812_10375_amd.lbm import BatchLattice
+    scs = _mixed("f32")
+    eager = BatchLattice(scs)
+    want = []
+    for _ in range(2):
+        eager.step(HIST)
+        want.append((eager.observe(), [eager.read(i, "T") for i in range(len(scs))]))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    bat = BatchLattice(scs, stream=s)
+    bat.observe()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bat.step(HIST)
+    for r in range(2):
+        with torch.cuda.stream(s):
+            g.replay()
+        obs = bat.observe()
+        wo, wT = want[r]
+        for i in range(len(scs)):
+            assert obs[i]["step"] == (r + 1) * HIST
+            assert np.array_equal(bat.read(i, "T"), wT[i]), (r, i)
+            assert obs[i]["energy"] == wo[i]["energy"]
+
+
+def test_autotuner_picks_a_candidate_and_caches_it():
+    from paper_1812_10375_amd.lbm import autotune_tile_rows
+    scs = _mixed("f32", rows=0)
+    rows, ms = autotune_tile_rows(scs, steps=5)
+    log("[batch] autotune rows=%d ms=%.4f" % (rows, ms))
+    assert rows in (8, 12, 16, 20, 24, 32, 40, 48)
+    assert ms > 0
+    assert autotune_tile_rows(scs, steps=5) == (rows, ms)
