@@ -25,6 +25,8 @@ UNITS = [
     # FP32 divide and square root at hardware rate (about 1 ulp) in the FP32 path
     ("lbm_f32.hip", ["-fno-hip-fp32-correctly-rounded-divide-sqrt"]),
     ("lbm_f64.hip", ["-ffp-contract=off"]),
+    # the surrogate's BF16 matrix-core kernels
+    ("mlp.hip", []),
 ]
 
 

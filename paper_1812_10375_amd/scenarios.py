@@ -81,6 +81,13 @@ def sample_sites(rng, nx, n_sites, min_spacing, width, gmins=(0.0, -0.3, -0.6)):
                     dtype=np.float64)
 
 
+def regular_sites(nx, spacing, width, gmins=(0.0, -0.3, -0.6)):
+    """Evenly spaced sites: centres at spacing/2 + k*spacing, k < nx // spacing."""
+    n = max(1, nx // spacing)
+    return np.array([[spacing / 2.0 + k * spacing, width, gmins[k % len(gmins)]] for k in range(n)],
+                    dtype=np.float64)
+
+
 def interface_conduction(nx=8, ny=256, exact_energy=True, steps=5000, precision="f64"):
     """1-D heat conduction across a flat liquid-vapour interface (Sec. 3.2 analogue,
     y-oriented): walls at both ends held at 0.87 Tc and 0.85 Tc, liquid lower half,
@@ -110,17 +117,23 @@ def film_evaporation(nx=256, ny=256, film=40, superheat=0.05, seed=2, steps=2000
 
 def pool_boiling(nx=1024, ny=1024, heater_rows=25, superheat=0.10, g=3e-5, n_sites=8,
                  min_spacing=64, site_width=4.0, liquid_fraction=0.7, seed=3, steps=100000,
-                 precision="f32"):
+                 precision="f32", site_spacing=None, Gw0=GW0):
     """Pool boiling on a conjugate heater with nucleation sites (Sec. 4.2 family):
     heater rows below the fluid, its bottom held at T_s + superheat*Tc, convective
-    outlet at the top, gravity along -y, liquid filling the lower fraction."""
+    outlet at the top, gravity along -y, liquid filling the lower fraction.  Sites are
+    sampled with a minimum spacing, or evenly spaced when ``site_spacing`` is given."""
     rng = np.random.default_rng(seed)
-    sites = sample_sites(rng, nx, n_sites, min_spacing, site_width) if n_sites else np.zeros((0, 3))
+    if site_spacing:
+        sites = regular_sites(nx, int(site_spacing), site_width)
+    elif n_sites:
+        sites = sample_sites(rng, nx, n_sites, min_spacing, site_width)
+    else:
+        sites = np.zeros((0, 3))
     n_liq = int(round(liquid_fraction * ny))
     return base_params(
         name="pool_boiling_%dx%d" % (nx, ny), nx=nx, ny=ny, heater_rows=heater_rows,
         top_bc="convective", bottom_tbc="dirichlet", top_tbc="zero_grad",
-        T_bottom=T_SAT + superheat * TC, Gw0=GW0, g=g, sites=sites,
+        T_bottom=T_SAT + superheat * TC, Gw0=Gw0, g=g, sites=sites,
         rho0=layered_density(nx, ny, n_liq), T0=np.full((heater_rows + ny, nx), T_SAT),
         precision=precision, steps=steps, seed=seed)
 
@@ -145,6 +158,29 @@ def batched_pool_boiling(n=48, seed=7, heater_rows=25, precision="f32", steps=50
         sc["name"] = "batch%02d_%s" % (i, sc["name"])
         out.append(sc)
     return out
+
+
+# Surrogate network parameter vector of one member (row-major; a layer computes
+# z = h W + b for a row vector h): W1[4][128], b1[128], W2[128][128], b2[128],
+# W3[128][2], b3[2].
+MLP_SHAPES = ((4, 128), (128,), (128, 128), (128,), (128, 2), (2,))
+
+
+def mlp_init_params(seed, members):
+    """Seeded initial weights of an ensemble: weights uniform within the Glorot bounds
+    +-sqrt(6 / (fan_in + fan_out)), biases zero; returns members x 17410 float64."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for _ in range(members):
+        parts = []
+        for shape in MLP_SHAPES:
+            if len(shape) == 2:
+                lim = np.sqrt(6.0 / (shape[0] + shape[1]))
+                parts.append(rng.uniform(-lim, lim, size=shape).ravel())
+            else:
+                parts.append(np.zeros(shape))
+        rows.append(np.concatenate(parts))
+    return np.array(rows)
 
 
 def static_droplet(nx, ny, radius, seed=None, precision="f64", bubble=False):
