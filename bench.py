@@ -117,6 +117,41 @@ def batched(steps=200, warmup=20):
     return out
 
 
+def boiling_curve(n_train=2048, n_query=10000, threshold=0.0075):
+    """Boiling-curve points per hour: the plain per-run GPU form (one single-domain run
+    per point) against batched runs of the method plus the surrogate ensemble (trained
+    on batched runs, falling back to batched runs where its members disagree), with the
+    surrogate's error against 16 held-out plain runs."""
+    import numpy as np
+    from paper_1812_10375_amd import surrogate as SG
+    proto = SG.Protocol()
+    Xh = SG.sample_inputs(16, seed=99)
+    single = [SG.timed(SG.run_plain_single, Xh[i], proto)[1] for i in range(3)]
+    t_single = float(np.median(single))
+    X = SG.sample_inputs(n_train, seed=1)
+    (Y, _), t_data = SG.timed(SG.run_plain, X, proto)
+    sur = SG.Surrogate(members=4, seed=3)
+    _, t_train = SG.timed(sur.fit, X, Y)
+    Xq = SG.sample_inputs(n_query, seed=5)
+    (vals, fall), t_query = SG.timed(SG.boiling_curve, sur, Xq, proto, threshold)
+    (Yh, _), _ = SG.timed(SG.run_plain, Xh, proto)
+    vh, fh = SG.boiling_curve(sur, Xh, proto, threshold)
+    err = np.abs(vh[:, 0] - Yh[:, 0]) / np.abs(Yh[:, 0])
+    t_sur = t_data + t_train + t_query
+    plain = 3600.0 / t_single
+    return {"protocol": "%dx%d+%d full pool, %d steps, window %d" % (proto.nx, proto.ny, proto.heater_rows,
+                                                                   proto.steps, proto.window),
+            "plain_pts_per_hour": plain,
+            "batched_pts_per_hour": n_train * 3600.0 / t_data,
+            "batched_surrogate_pts_per_hour": n_query * 3600.0 / t_sur,
+            "gain_vs_plain": n_query * 3600.0 / t_sur / plain,
+            "queries": n_query, "train_runs": n_train, "fallback_fraction": len(fall) / n_query,
+            "spread_threshold": threshold,
+            "seconds": {"single_run": t_single, "train_data": t_data, "train": t_train, "query": t_query},
+            "heldout_rel_err_mean": float(err.mean()), "heldout_rel_err_max": float(err.max()),
+            "heldout_fallbacks": int(len(fh))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +163,8 @@ def main():
     ap.add_argument("--ny", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-domain measurement")
+    ap.add_argument("--no-boiling-curve", action="store_true",
+                    help="skip the boiling-curve points/hour comparison (plain vs batched + surrogate)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes five times "
@@ -199,7 +236,7 @@ def main():
                     "kernel": "k_energy_rows", "per_launch": af, "avg_launch_ms": per[dom]}
     step_bytes = algorithmic_bytes(sc) + 8 * sc["nx"] * (sc["ny"] + sc["heater_rows"])
     out = {
-        "metric": "MLUPS 1024^2 FP32 plain",
+        "metric": "MLUPS 1024\u00b2 FP32 plain; boiling-curve pts/hr batched+surrogate vs plain",
         "value": mlups,
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -223,6 +260,8 @@ def main():
     lat.close()
     if not args.no_batched:
         out["batched"] = batched()
+    if not args.no_boiling_curve:
+        out["boiling_curve"] = boiling_curve()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
     print(json.dumps(out))

@@ -53,10 +53,12 @@ int lbm_mlp_get_params(lbm_mlp *m, float *host);
 /* d_x: device [B][4] FP32 inputs; d_y: device [members][B][2] FP32 outputs. */
 int lbm_mlp_forward(lbm_mlp *m, const float *d_x, int B, float *d_y);
 
-/* Forward and backward pass of every member on the same batch: d_t device [B][2] FP32
- * targets; gradients of the loss go to the library's gradient buffers, the loss of
- * each member to d_loss (device, members floats). */
-int lbm_mlp_backward(lbm_mlp *m, const float *d_x, const float *d_t, int B, float *d_loss);
+/* Forward and backward pass of every member: d_x device [B][4] inputs and d_t device
+ * [B][2] FP32 targets shared by all members (per_member = 0), or [members][B][4] and
+ * [members][B][2] with a batch of its own for each member (per_member = 1, e.g.
+ * bootstrap resamples).  Gradients of each member's loss go to the library's gradient
+ * buffers, the losses to d_loss (device, members floats). */
+int lbm_mlp_backward(lbm_mlp *m, const float *d_x, const float *d_t, int B, int per_member, float *d_loss);
 
 /* Copy the gradients of the last lbm_mlp_backward to the host (host parameter layout). */
 int lbm_mlp_get_grads(lbm_mlp *m, float *host);

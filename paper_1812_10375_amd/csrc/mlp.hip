@@ -107,19 +107,21 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const Gemm g) {
   }
 }
 
-// inputs [B][4] FP32 -> [B][32] BF16, zero beyond column 4
-__global__ void k_prep_x(const float* __restrict__ x, __bf16* __restrict__ xb, int B) {
+// inputs [B][4] FP32 (member z at x + z * sx) -> [B][32] BF16 (member z at xb + z * sxb),
+// zero beyond column 4; blockIdx.y = member
+__global__ void k_prep_x(const float* __restrict__ x, long sx, __bf16* __restrict__ xb, long sxb, int B) {
+  const int z = blockIdx.y;
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < (long)B * KP1; t += (long)gridDim.x * blockDim.x) {
     const int c = (int)(t % KP1);
     const long b = t / KP1;
-    xb[t] = (__bf16)(c < IN ? x[b * IN + c] : 0.f);
+    xb[z * sxb + t] = (__bf16)(c < IN ? x[z * sx + b * IN + c] : 0.f);
   }
 }
 
 // dY = 2 (Y - T) / B on the 2 outputs (zero on the padded columns), and the loss of
 // each member: one block per member, fixed-order reduction.
-__global__ void __launch_bounds__(256) k_out_grad(const float* __restrict__ Y, const float* __restrict__ T, int B,
-                                                   float* __restrict__ dYf, __bf16* __restrict__ dYb,
+__global__ void __launch_bounds__(256) k_out_grad(const float* __restrict__ Y, const float* __restrict__ T, long st,
+                                                   int B, float* __restrict__ dYf, __bf16* __restrict__ dYb,
                                                    float* __restrict__ loss, long sy, long sd) {
   __shared__ float red[256];
   const int z = blockIdx.x;
@@ -130,7 +132,7 @@ __global__ void __launch_bounds__(256) k_out_grad(const float* __restrict__ Y, c
     const int c = (int)(t % NP3);
     float d = 0.f;
     if (c < OUT) {
-      const float e = Y[z * sy + b * OUT + c] - T[b * OUT + c];
+      const float e = Y[z * sy + b * OUT + c] - T[z * st + b * OUT + c];
       acc += e * e;
       d = 2.f * e * inv;
     }
@@ -196,7 +198,7 @@ Layout layout(int M, int Bm) {
   L.m1 = take(P * 4);
   L.m2 = take(P * 4);
   L.wb = take(P * 2);
-  L.xb = take((size_t)Bm * KP1 * 2);
+  L.xb = take(A * KP1 * 2);
   L.z1 = take(A * H * 4);
   L.h1 = take(A * H * 2);
   L.z2 = take(A * H * 4);
@@ -244,15 +246,16 @@ Gemm blank() {
 
 // forward pass of every member: Z1, H1, Z2, H2 into the workspace, outputs to y
 // ([members][B][2] with member stride sy)
-void forward(lbm_mlp* m, const float* x, int B, float* y, long sy) {
+void forward(lbm_mlp* m, const float* x, long sx, int B, float* y, long sy) {
   const Layout& L = m->L;
   const long A = (long)m->max_batch;  // member stride of the activation arrays, in rows
-  hipLaunchKernelGGL(k_prep_x, dim3(256), dim3(256), 0, m->stream, x, m->at<__bf16>(L.xb), B);
+  hipLaunchKernelGGL(k_prep_x, dim3(256, m->members), dim3(256), 0, m->stream, x, sx, m->at<__bf16>(L.xb), A * KP1,
+                     B);
   const __bf16* wb = m->at<__bf16>(L.wb);
   const float* w = m->at<float>(L.w);
   Gemm g = blank();
   // layer 1: Z1 = X W1 + b1, H1 = gelu(Z1)
-  g.A = m->at<__bf16>(L.xb); g.sam = KP1; g.sak = 1; g.saz = 0;
+  g.A = m->at<__bf16>(L.xb); g.sam = KP1; g.sak = 1; g.saz = A * KP1;
   g.B = wb + OFF_W1; g.sbk = H; g.sbn = 1; g.sbz = PP;
   g.M = B; g.N = H; g.K = KP1;
   g.bias = w + OFF_B1; g.sbias = PP;
@@ -387,17 +390,18 @@ int lbm_mlp_get_grads(lbm_mlp* m, float* host) {
 
 int lbm_mlp_forward(lbm_mlp* m, const float* d_x, int B, float* d_y) {
   if (!m || !d_x || !d_y || B < 1 || B > m->max_batch) return LBM_EINVAL;
-  forward(m, d_x, B, d_y, (long)B * OUT);
+  forward(m, d_x, 0, B, d_y, (long)B * OUT);
   return hip_rc(hipGetLastError());
 }
 
-int lbm_mlp_backward(lbm_mlp* m, const float* d_x, const float* d_t, int B, float* d_loss) {
+int lbm_mlp_backward(lbm_mlp* m, const float* d_x, const float* d_t, int B, int per_member, float* d_loss) {
   if (!m || !d_x || !d_t || !d_loss || B < 1 || B > m->max_batch) return LBM_EINVAL;
   const Layout& L = m->L;
   const long A = (long)m->max_batch;
   float* Y = m->at<float>(L.y);
-  forward(m, d_x, B, Y, A * OUT);
-  hipLaunchKernelGGL(k_out_grad, dim3(m->members), dim3(256), 0, m->stream, Y, d_t, B, m->at<float>(L.dyf),
+  const long sx = per_member ? (long)B * IN : 0, st = per_member ? (long)B * OUT : 0;
+  forward(m, d_x, sx, B, Y, A * OUT);
+  hipLaunchKernelGGL(k_out_grad, dim3(m->members), dim3(256), 0, m->stream, Y, d_t, st, B, m->at<float>(L.dyf),
                      m->at<__bf16>(L.dyb), d_loss, A * OUT, A * NP3);
   float* gr = m->at<float>(L.g);
   const __bf16* wb = m->at<__bf16>(L.wb);
@@ -439,7 +443,7 @@ int lbm_mlp_backward(lbm_mlp* m, const float* d_x, const float* d_t, int B, floa
   gemm<EPI_GELU_GRAD>(m, g);
   // dW1 = X^T dZ1 (32 x 128; rows 4..31 are zero since the padded inputs are)
   g = blank();
-  g.A = m->at<__bf16>(L.xb); g.sam = 1; g.sak = KP1; g.saz = 0;
+  g.A = m->at<__bf16>(L.xb); g.sam = 1; g.sak = KP1; g.saz = A * KP1;
   g.B = m->at<__bf16>(L.d1b); g.sbk = H; g.sbn = 1; g.sbz = A * H;
   g.M = KP1; g.N = H; g.K = B;
   g.Cf = gr + OFF_W1; g.ldc = H; g.scf = PP;

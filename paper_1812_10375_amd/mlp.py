@@ -31,7 +31,7 @@ def _lib():
         L.lbm_mlp_forward.restype = C.c_int
         L.lbm_mlp_forward.argtypes = [vp, vp, C.c_int, vp]
         L.lbm_mlp_backward.restype = C.c_int
-        L.lbm_mlp_backward.argtypes = [vp, vp, vp, C.c_int, vp]
+        L.lbm_mlp_backward.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp]
         L.lbm_mlp_adam.restype = C.c_int
         L.lbm_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
         L.lbm_mlp_destroy.restype = C.c_int
@@ -105,11 +105,13 @@ class MLPEnsemble:
             raise LbmError(rc, "lbm_mlp_get_grads")
         return a.astype(np.float64)
 
-    def _dev(self, x, cols):
+    def _dev(self, x, cols, allow_members=False):
         t = self.torch.as_tensor(np.asarray(x, dtype=np.float32)) if not self.torch.is_tensor(x) else x
         t = t.to(device=self.device, dtype=self.torch.float32).contiguous()
-        if t.dim() != 2 or t.shape[1] != cols:
-            raise ValueError("expected a [B][%d] array" % cols)
+        ok = (t.dim() == 2 and t.shape[1] == cols) or (
+            allow_members and t.dim() == 3 and t.shape[0] == self.members and t.shape[2] == cols)
+        if not ok:
+            raise ValueError("expected a [B][%d] array%s" % (cols, " or [members][B][%d]" % cols if allow_members else ""))
         return t
 
     def forward(self, x):
@@ -124,10 +126,15 @@ class MLPEnsemble:
         return y
 
     def backward(self, x, t):
-        """Loss and gradients of every member on (x, t); returns the device loss tensor."""
-        xt, tt = self._dev(x, 4), self._dev(t, 2)
-        B = xt.shape[0]
-        rc = _lib().lbm_mlp_backward(self.h, C.c_void_p(xt.data_ptr()), C.c_void_p(tt.data_ptr()), B,
+        """Loss and gradients of every member on (x, t): arrays [B][4], [B][2] shared by
+        all members, or [members][B][4], [members][B][2] with one batch per member.
+        Returns the device loss tensor."""
+        xt, tt = self._dev(x, 4, True), self._dev(t, 2, True)
+        per = int(xt.dim() == 3)
+        if tt.dim() != xt.dim() or tt.shape[-2] != xt.shape[-2]:
+            raise ValueError("inputs and targets do not match")
+        B = xt.shape[-2]
+        rc = _lib().lbm_mlp_backward(self.h, C.c_void_p(xt.data_ptr()), C.c_void_p(tt.data_ptr()), B, per,
                                      C.c_void_p(self.loss.data_ptr()))
         if rc != 0:
             raise LbmError(rc, "lbm_mlp_backward")
