@@ -43,13 +43,30 @@ __global__ void __launch_bounds__(NT)
       reinterpret_cast<long long*>(ws + L.dstep[cur]), g - D.tile0L);
 }
 
-// Energy update of every domain (FP32 register-row kernel).  fcur names the buffer that
-// holds the populations after this step's collision (read by the open-top rule).
+// Energy update of every domain.  Blocks [0, ndom) apply the open-top rule of domain b
+// (once per LB step); the remaining blocks take the tiles.  fpost names the population
+// buffer written by this step's collision (read by the open-top rule).
+template <typename real, int NW>
+__device__ __forceinline__ bool batch_outlet(const DomainDev* __restrict__ tab, int ndom, int fpost, int cur,
+                                             int sub) {
+  if ((int)blockIdx.x >= ndom) return false;
+  const DomainDev& D = tab[blockIdx.x];
+  const Layout& L = D.L;
+  char* ws = D.ws;
+  if (sub == 0)
+    outlet_block<real, NW>(D.P, reinterpret_cast<const real*>(ws + L.f[fpost]), reinterpret_cast<real*>(ws + L.topin),
+                           reinterpret_cast<const real*>(ws + L.ux), reinterpret_cast<const real*>(ws + L.uy),
+                           reinterpret_cast<const double*>(ws + L.partL[cur]), reinterpret_cast<double*>(ws + L.pmin[cur]));
+  return true;
+}
+
+// FP32 register-row kernel
 template <int NW, int B, int WPE>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
     k_energy_rows_batch(const DomainDev* __restrict__ tab, int ndom, int fpost, int tcur, int cur,
                         int hslot, int sub, double dtd) {
-  const int g = xcd_tile(blockIdx.x, gridDim.x);
+  if (batch_outlet<float, NW>(tab, ndom, fpost, cur, sub)) return;
+  const int g = xcd_tile(blockIdx.x - ndom, gridDim.x - ndom);
   const int d = batch_domain<true>(tab, ndom, g);
   const DomainDev& D = tab[d];
   const Layout& L = D.L;
@@ -58,19 +75,17 @@ __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WP
       D.P, reinterpret_cast<const float*>(ws + L.T[tcur]), reinterpret_cast<float*>(ws + L.T[1 - tcur]),
       reinterpret_cast<const float*>(ws + L.rho), reinterpret_cast<const float*>(ws + L.ux),
       reinterpret_cast<const float*>(ws + L.uy),
-      reinterpret_cast<double*>(ws + L.hist) + (size_t)hslot * D.P.nblkE * 5,
-      reinterpret_cast<const float*>(ws + L.f[fpost]), reinterpret_cast<float*>(ws + L.topin),
-      reinterpret_cast<const double*>(ws + L.partL[cur]), reinterpret_cast<double*>(ws + L.pmin[cur]),
-      reinterpret_cast<DevDiag*>(ws + L.diag), sub, dtd,
-      reinterpret_cast<const long long*>(ws + L.dstep[1 - cur]), g - D.tile0E);
+      reinterpret_cast<double*>(ws + L.hist) + (size_t)hslot * D.P.nblkE * 5, reinterpret_cast<DevDiag*>(ws + L.diag),
+      sub, dtd, reinterpret_cast<const long long*>(ws + L.dstep[1 - cur]), g - D.tile0E);
 }
 
-// Energy update of every domain (LDS kernel: FP64, or the isotropic scheme).
+// LDS kernel (FP64, or the isotropic scheme)
 template <typename real, bool ISO, int NW, int HMAX>
 __global__ void __launch_bounds__(NW * 64)
     k_energy_batch(const DomainDev* __restrict__ tab, int ndom, int fpost, int tcur, int cur, int hslot,
                    int sub, double dtd) {
-  const int g = xcd_tile(blockIdx.x, gridDim.x);
+  if (batch_outlet<real, NW>(tab, ndom, fpost, cur, sub)) return;
+  const int g = xcd_tile(blockIdx.x - ndom, gridDim.x - ndom);
   const int d = batch_domain<true>(tab, ndom, g);
   const DomainDev& D = tab[d];
   const Layout& L = D.L;
@@ -79,11 +94,8 @@ __global__ void __launch_bounds__(NW * 64)
       D.P, reinterpret_cast<const real*>(ws + L.T[tcur]), reinterpret_cast<real*>(ws + L.T[1 - tcur]),
       reinterpret_cast<const real*>(ws + L.rho), reinterpret_cast<const real*>(ws + L.ux),
       reinterpret_cast<const real*>(ws + L.uy),
-      reinterpret_cast<double*>(ws + L.hist) + (size_t)hslot * D.P.nblkE * 5,
-      reinterpret_cast<const real*>(ws + L.f[fpost]), reinterpret_cast<real*>(ws + L.topin),
-      reinterpret_cast<const double*>(ws + L.partL[cur]), reinterpret_cast<double*>(ws + L.pmin[cur]),
-      reinterpret_cast<DevDiag*>(ws + L.diag), sub, dtd,
-      reinterpret_cast<const long long*>(ws + L.dstep[1 - cur]), g - D.tile0E);
+      reinterpret_cast<double*>(ws + L.hist) + (size_t)hslot * D.P.nblkE * 5, reinterpret_cast<DevDiag*>(ws + L.diag),
+      sub, dtd, reinterpret_cast<const long long*>(ws + L.dstep[1 - cur]), g - D.tile0E);
 }
 
 }  // namespace lbmk

@@ -341,9 +341,8 @@ template <int NW, int B>
 __device__ __forceinline__ void energy_rows_step(
     const KParams& P, const float* __restrict__ Tin, float* __restrict__ Tout,
     const float* __restrict__ rho, const float* __restrict__ uxa, const float* __restrict__ uya,
-    double* __restrict__ hist_slot, const float* __restrict__ fpost, float* __restrict__ topin,
-    const double* __restrict__ partL_cur, double* __restrict__ pmin_cur, DevDiag* __restrict__ diag,
-    int sub, double dtd, const long long* __restrict__ dstep_prev, int tile) {
+    double* __restrict__ hist_slot, DevDiag* __restrict__ diag, int sub, double dtd,
+    const long long* __restrict__ dstep_prev, int tile) {
   __shared__ RowsShared<NW, B> sh;
   const int nT = P.nT, TY = P.tyE;
   const int x0 = (tile % P.ntxE) * P.txE, j0 = (tile / P.ntxE) * TY;
@@ -355,28 +354,6 @@ __device__ __forceinline__ void energy_rows_step(
     energy_rows_tile<NW, B, false>(P, sh, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
                                    tile, x0, j0);
 
-  // Tiles holding the top fluid row set the open-top inflow of the next step for
-  // their own columns (once per LB step).
-  if (sub == 0 && j0 <= nT - 1 && nT - 1 < j0 + TY) {
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int nx = P.nx;
-    const bool lane_out = lane >= 4 && lane < 4 + P.txE && x0 + lane - 4 < nx;
-    double ms[1] = {0.0};
-    if (P.top_bc != TOP_WALL && w == 0 && lane_out) {
-      float U = 0.f;
-      if (P.top_bc == TOP_CONVECTIVE) {
-        // mean outflow velocity of the row below the top, from the collide partials
-        const int ry = (P.ny - 2) / P.tyL;
-        double us = 0.0;
-        for (int bx = 0; bx < P.ntxL; ++bx) us += partL_cur[3 * (ry * P.ntxL + bx) + 2];
-        us /= nx;
-        U = (float)(us > 0.0 ? us : 0.0);
-      }
-      ms[0] = outlet_column(P, x0 + lane - 4, U, fpost, topin, uxa, uya);
-    }
-    block_sum_n<1, NW>(ms, sh.red);
-    if (t == 0) pmin_cur[tile % P.ntxE] = ms[0];
-  }
 }
 
 template <int NW, int B, int WPE>
@@ -388,8 +365,13 @@ __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WP
                   const double* __restrict__ partL_cur, double* __restrict__ pmin_cur,
                   DevDiag* __restrict__ diag, int sub, double dtd,
                   const long long* __restrict__ dstep_prev) {
-  energy_rows_step<NW, B>(P, Tin, Tout, rho, uxa, uya, hist_slot, fpost, topin, partL_cur, pmin_cur, diag, sub,
-                          dtd, dstep_prev, xcd_tile(blockIdx.x, P.nblkE));
+  // block 0: the open-top rule; blocks 1..nblkE: the tiles
+  if (blockIdx.x == 0) {
+    if (sub == 0) outlet_block<float, NW>(P, fpost, topin, uxa, uya, partL_cur, pmin_cur);
+    return;
+  }
+  energy_rows_step<NW, B>(P, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
+                          xcd_tile(blockIdx.x - 1, P.nblkE));
 }
 
 }  // namespace lbmk

@@ -666,9 +666,8 @@ template <typename real, bool ISO, int NW, int HMAX>
 __device__ __forceinline__ void energy_lds_tile(
     const KParams& P, const real* __restrict__ Tin, real* __restrict__ Tout,
     const real* __restrict__ rho, const real* __restrict__ uxa, const real* __restrict__ uya,
-    double* __restrict__ hist_slot, const real* __restrict__ fpost, real* __restrict__ topin,
-    const double* __restrict__ partL_cur, double* __restrict__ pmin_cur, DevDiag* __restrict__ diag,
-    int sub, double dtd, const long long* __restrict__ dstep_prev, int tile) {
+    double* __restrict__ hist_slot, DevDiag* __restrict__ diag, int sub, double dtd,
+    const long long* __restrict__ dstep_prev, int tile) {
   constexpr int H4M = HMAX + 8;
   constexpr int NR4 = (H4M + NW - 1) / NW;        // LDS rows per wave (load, faces)
   constexpr int NC = (HMAX + 6 + NW - 1) / NW;    // stage-1 rows per wave
@@ -980,24 +979,42 @@ __device__ __forceinline__ void energy_lds_tile(
       pe[4] += v[4];
     }
   }
-  // Tiles holding the top fluid row set the open-top inflow of the next step for
-  // their own columns (once per LB step).
-  if (sub == 0 && j0 <= nT - 1 && nT - 1 < j0 + TY) {
-    double ms[1] = {0.0};
-    if (top_open && w == 0 && lane_out) {
-      real U = real(0);
-      if (P.top_bc == TOP_CONVECTIVE) {
-        // mean outflow velocity of the row below the top, from the collide partials
-        const int ry = (P.ny - 2) / P.tyL;
-        double us = 0.0;
-        for (int bx = 0; bx < P.ntxL; ++bx) us += partL_cur[3 * (ry * P.ntxL + bx) + 2];
-        us /= nx;
-        U = (real)(us > 0.0 ? us : 0.0);
-      }
-      ms[0] = outlet_column(P, x0 + lane - 4, U, fpost, topin, uxa, uya);
+}
+
+// Open top: the populations entering the top row at the next step, for every column, and
+// the net inflow of each energy tile column (FP64, lanes summed in a fixed order).  Run
+// by one whole workgroup of NW waves beside the tiles of the energy launch, once per LB
+// step, so that its chain of dependent loads does not lengthen any tile.
+template <typename real, int NW>
+__device__ __forceinline__ void outlet_block(const KParams& P, const real* __restrict__ fpost,
+                                             real* __restrict__ topin, const real* __restrict__ uxa,
+                                             const real* __restrict__ uya, const double* __restrict__ partL_cur,
+                                             double* __restrict__ pmin_cur) {
+  __shared__ double uo;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (P.top_bc == TOP_WALL) {  // closed top: no exchange
+    for (int b = t; b < P.ntxE; b += NW * 64) pmin_cur[b] = 0.0;
+    return;
+  }
+  real U = real(0);
+  if (P.top_bc == TOP_CONVECTIVE) {
+    if (t == 0) {
+      // mean outflow velocity of the row below the top, from the collide partials
+      const int ry = (P.ny - 2) / P.tyL;
+      double us = 0.0;
+      for (int bx = 0; bx < P.ntxL; ++bx) us += partL_cur[3 * (ry * P.ntxL + bx) + 2];
+      us /= P.nx;
+      uo = us > 0.0 ? us : 0.0;
     }
-    block_sum_n<1, NW>(ms, red);
-    if (t == 0) pmin_cur[tile % P.ntxE] = ms[0];
+    __syncthreads();
+    U = (real)uo;
+  }
+  for (int b = w; b < P.ntxE; b += NW) {
+    const int x = b * P.txE + lane;
+    double d = 0.0;
+    if (lane < P.txE && x < P.nx) d = outlet_column(P, x, U, fpost, topin, uxa, uya);
+    d = wave_sum(d);
+    if (lane == 0) pmin_cur[b] = d;
   }
 }
 
@@ -1010,8 +1027,13 @@ __global__ void __launch_bounds__(NW * 64)
              const double* __restrict__ partL_cur, double* __restrict__ pmin_cur,
              DevDiag* __restrict__ diag, int sub, double dtd,
              const long long* __restrict__ dstep_prev) {
-  energy_lds_tile<real, ISO, NW, HMAX>(P, Tin, Tout, rho, uxa, uya, hist_slot, fpost, topin, partL_cur,
-                                       pmin_cur, diag, sub, dtd, dstep_prev, xcd_tile(blockIdx.x, P.nblkE));
+  // block 0: the open-top rule; blocks 1..nblkE: the tiles
+  if (blockIdx.x == 0) {
+    if (sub == 0) outlet_block<real, NW>(P, fpost, topin, uxa, uya, partL_cur, pmin_cur);
+    return;
+  }
+  energy_lds_tile<real, ISO, NW, HMAX>(P, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
+                                       xcd_tile(blockIdx.x - 1, P.nblkE));
 }
 
 // ---------------------------------------------------------------------------

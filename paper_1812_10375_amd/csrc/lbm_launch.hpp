@@ -65,14 +65,14 @@ void step_once(lbm_ctx* h) {
     real* Tout = h->at<real>(L.T[1 - h->tcur]);
     tev = timing_begin(h, 1);
 #define LBM_E(ISO)                                                                               \
-  hipLaunchKernelGGL((lbmk::k_energy<real, ISO, E_NW, E_HMAX>), dim3(P.nblkE), dim3(E_NW * 64), 0, \
+  hipLaunchKernelGGL((lbmk::k_energy<real, ISO, E_NW, E_HMAX>), dim3(P.nblkE + 1), dim3(E_NW * 64), 0, \
                      h->stream, P, Tin, Tout, rho, ux, uy, hslot, fd, topin,                       \
                      h->at<double>(L.partL[cur]), h->at<double>(L.pmin[cur]), diag, sub, dt,      \
                      h->at<long long>(L.dstep[prev]))
     if (iso) LBM_E(true);
     else if constexpr (f64) LBM_E(false);
     else
-      hipLaunchKernelGGL((lbmk::k_energy_rows<E_RNW, E_BAND, E_RWPE>), dim3(P.nblkE), dim3(E_RNW * 64), 0, h->stream, P,
+      hipLaunchKernelGGL((lbmk::k_energy_rows<E_RNW, E_BAND, E_RWPE>), dim3(P.nblkE + 1), dim3(E_RNW * 64), 0, h->stream, P,
                          Tin, Tout, rho, ux, uy, hslot, fd, topin, h->at<double>(L.partL[cur]),
                          h->at<double>(L.pmin[cur]), diag, sub, dt, h->at<long long>(L.dstep[prev]));
 #undef LBM_E
@@ -102,13 +102,13 @@ void batch_step_once(lbm_batch* b) {
   const double dt = 1.0 / h0->cfg.n_sub;
   for (int sub = 0; sub < h0->cfg.n_sub; ++sub) {
     if (iso)
-      hipLaunchKernelGGL((lbmk::k_energy_batch<real, true, E_NW, E_HMAX>), dim3(b->nblkE), dim3(E_NW * 64), 0,
+      hipLaunchKernelGGL((lbmk::k_energy_batch<real, true, E_NW, E_HMAX>), dim3(b->nblkE + n), dim3(E_NW * 64), 0,
                          b->stream, b->table, n, 1 - fcur, tcur, cur, hslot, sub, dt);
     else if constexpr (f64)
-      hipLaunchKernelGGL((lbmk::k_energy_batch<real, false, E_NW, E_HMAX>), dim3(b->nblkE), dim3(E_NW * 64), 0,
+      hipLaunchKernelGGL((lbmk::k_energy_batch<real, false, E_NW, E_HMAX>), dim3(b->nblkE + n), dim3(E_NW * 64), 0,
                          b->stream, b->table, n, 1 - fcur, tcur, cur, hslot, sub, dt);
     else
-      hipLaunchKernelGGL((lbmk::k_energy_rows_batch<E_RNW, E_BAND, E_RWPE>), dim3(b->nblkE), dim3(E_RNW * 64), 0,
+      hipLaunchKernelGGL((lbmk::k_energy_rows_batch<E_RNW, E_BAND, E_RWPE>), dim3(b->nblkE + n), dim3(E_RNW * 64), 0,
                          b->stream, b->table, n, 1 - fcur, tcur, cur, hslot, sub, dt);
     tcur = 1 - tcur;
   }
