@@ -117,6 +117,40 @@ def batched(steps=200, warmup=20):
     return out
 
 
+def hbm_resident(n=4096, steps=100, warmup=10):
+    """The same workload at n x n, whose working set (about 1.3 GB at 4096^2) is far
+    larger than the 256 MB last-level cache, so that the rates are HBM rates."""
+    import torch
+    from paper_1812_10375_amd import scenarios as S
+    from paper_1812_10375_amd.lbm import Lattice
+    sc = S.pool_boiling(nx=n, ny=n)
+    lat = Lattice(sc)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    lat.step(steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    lat.set_kernel_timing(True)
+    lat.kernel_times()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    kt = lat.kernel_times()
+    ob = lat.observe(check=False)
+    lat.close()
+    per = {k: v[0] / v[1] for k, v in kt.items() if v[1]}
+    ab = algorithmic_bytes(sc)
+    step_bytes = ab + 8 * sc["nx"] * (sc["ny"] + sc["heater_rows"])
+    return {"workload": sc["name"] + "+%d_heater" % sc["heater_rows"], "steps": steps,
+            "ms_per_step": ms / steps, "MLUPS": n * n * steps / (ms * 1e-3) / 1e6,
+            "kernels_ms": per,
+            "collide_algorithmic_GBps": ab / (per["collide"] * 1e-3) / 1e9,
+            "step_algorithmic_GBps": step_bytes / (ms / steps * 1e-3) / 1e9,
+            "status": ob["status"]}
+
+
 def boiling_curve(n_train=2048, n_query=10000, threshold=0.0075):
     """Boiling-curve points per hour: the plain per-run GPU form (one single-domain run
     per point) against batched runs of the method plus the surrogate ensemble (trained
@@ -162,6 +196,8 @@ def main():
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--ny", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbm-resident", action="store_true",
+                    help="skip the 4096 x 4096 measurement (working set beyond the last-level cache)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-domain measurement")
     ap.add_argument("--no-boiling-curve", action="store_true",
                     help="skip the boiling-curve points/hour comparison (plain vs batched + surrogate)")
@@ -258,6 +294,8 @@ def main():
         "status": ob["status"],
     }
     lat.close()
+    if not args.no_hbm_resident:
+        out["hbm_resident_4096"] = hbm_resident()
     if not args.no_batched:
         out["batched"] = batched()
     if not args.no_boiling_curve:

@@ -69,15 +69,19 @@ __device__ __forceinline__ void energy_rows_tile(
   // zero-gradient above an open top) ----
   float lT[B + 2], lR[B + 2], lU[B + 2], lV[B + 2];
   if constexpr (PLAIN) {
-    // rows outside the tile are clamped into the fluid rows; their values are unused
+    // rows outside the tile are clamped into the fluid rows; their values are unused.  A
+    // wave whose band lies wholly beyond the tile loads nothing.
 #pragma unroll
     for (int q = 0; q < B + 2; ++q) {
       const int j = min(max(jb - 1 + q, nh), nT - 1);
-      lT[q] = ld32(Tin, (unsigned)j * (unsigned)nx + gx);
-      const unsigned n = (unsigned)(j - nh) * (unsigned)nx + gx;
-      lR[q] = ld32(rho, n);
-      lU[q] = ld32(uxa, n);
-      lV[q] = ld32(uya, n);
+      lT[q] = 0.f; lR[q] = 1.f; lU[q] = 0.f; lV[q] = 0.f;
+      if (wave_live) {
+        lT[q] = ld32(Tin, (unsigned)j * (unsigned)nx + gx);
+        const unsigned n = (unsigned)(j - nh) * (unsigned)nx + gx;
+        lR[q] = ld32(rho, n);
+        lU[q] = ld32(uxa, n);
+        lV[q] = ld32(uya, n);
+      }
     }
   } else {
 #pragma unroll

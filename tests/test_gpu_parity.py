@@ -104,6 +104,28 @@ def _check32(sc, steps):
     return res, e
 
 
+def _trajectory32(sc, steps=1000, every=100):
+    """FP32 path against the oracle every `every` steps: max|drho|/rho_l (bound TOL32 at
+    every checkpoint) and max|dT| over the wall superheat (reported)."""
+    from oracle.lbm import OracleSim
+    from paper_1812_10375_amd.lbm import Lattice
+    log("[parity] %s nx=%d ny=%d nh=%d FP32 trajectory over %d steps" % (
+        sc.get("name", "?"), sc["nx"], sc["ny"], sc["heater_rows"], steps))
+    gpu, orc = Lattice(sc), OracleSim(sc)
+    dTw = abs(sc["T_bottom"] - S.T_SAT)
+    worst = 0.0
+    for n in range(every, steps + 1, every):
+        gpu.step(every)
+        assert orc.step(every) == 0, "oracle flagged an error"
+        gpu.observe()
+        er = np.abs(gpu.read("rho") - orc.field("rho")).max() / S.RHO_L
+        eT = np.abs(gpu.read("T") - orc.field("T")).max() / dTw
+        log("[parity]   step %4d  max|drho|/rho_l %.2e  max|dT|/dT_wall %.2e" % (n, er, eT))
+        assert er <= TOL32, (n, er)
+        worst = max(worst, er)
+    return worst
+
+
 def test_fp32_film_evaporation_1000_steps():
     sc = S.film_evaporation(steps=1000)     # 256 x 256, the film-evaporation workload
     _check32(sc, 1000)
@@ -112,6 +134,14 @@ def test_fp32_film_evaporation_1000_steps():
 def test_fp32_pool_boiling_cropped_1000_steps():
     sc = S.pool_boiling(nx=256, ny=256, n_sites=2, min_spacing=64, seed=3)
     _check32(sc, 1000)
+
+
+def test_fp32_error_trajectory_film_evaporation():
+    _trajectory32(S.film_evaporation(steps=1000))
+
+
+def test_fp32_error_trajectory_pool_boiling_cropped():
+    _trajectory32(S.pool_boiling(nx=256, ny=256, n_sites=2, min_spacing=64, seed=3))
 
 
 def test_fp32_pool_boiling_full_size_first_steps():
