@@ -92,7 +92,10 @@ enum {
  *                         fields do not depend on it, the FP64 sums behind the diagnostics
  *                         do, in their last bits); 0 = automatic (one domain: tiles that fill
  *                         the device in one round; a batch: the tallest tiles), otherwise
- *                         clamped to [8, 48]
+ *                         clamped to [8, 48].  It sets the number of tile rows; the FP32
+ *                         path (without LBM_DIFF_ISOTROPIC) then shortens the first and the
+ *                         last tile row, whose tiles run the slower boundary code, and
+ *                         raises the interior height to cover the grid (at most 48)
  */
 typedef struct {
   uint32_t struct_size, abi_version;

@@ -61,8 +61,32 @@ bool valid_config(const lbm_config* c) {
 // in one round (at least E_HMIN rows unless the grid is shorter).  ncu = 0 gives the
 // largest tile count any device can use (for sizing the workspace).
 struct Grids {
-  int ntxL, ntyL, ntxE, ntyE, txE, tyE;
+  int ntxL, ntyL, ntxE, ntyE, txE, tyE, tyE0;
 };
+
+// The FP32 register-row energy kernel runs tiles that reach within four rows of the
+// bottom or the top of the temperature grid, or of the heater-fluid interface, through
+// its general (per-row) code, about 1.3 times slower per row than the interior tiles.
+// With `rows` tile rows, shorten the first and the last tile row to edge heights of
+// about the cost of an interior tile, keeping the second tile row clear of the heater
+// (first height >= nh + 4) and the second-to-last clear of the top (last height >= 4),
+// and make the interior rows just tall enough to cover the grid.  Returns false
+// (uniform tiles) when no interior height up to hmax allows this.
+bool shape_edge_rows(int nT, int nh, int rows, int hmax, int& ty, int& ty0) {
+  if (rows < 3) return false;
+  for (int h = (nT + rows - 1) / rows; h <= hmax; ++h) {
+    const int cap = std::max(E_HMIN, (10 * (h + 8)) / 13 - 8);
+    if (nh + 4 > cap) continue;
+    const int edge = nT - (rows - 2) * h;  // rows left for the first and the last tile row
+    if (edge < nh + 8) return false;
+    if (edge <= 2 * cap) {
+      ty = h;
+      ty0 = std::max(nh + 4, (edge + 1) / 2);
+      return true;
+    }
+  }
+  return false;
+}
 
 Grids grids(const lbm_config* c, int ncu) {
   Grids g{};
@@ -87,6 +111,13 @@ Grids grids(const lbm_config* c, int ncu) {
   }
   g.tyE = (nT + rows - 1) / rows;
   g.ntyE = (nT + g.tyE - 1) / g.tyE;
+  g.tyE0 = g.tyE;
+  const bool row_kernel = !f64 && !(c->flags & LBM_DIFF_ISOTROPIC);
+  int ty_in, ty_edge;
+  if (ncu > 0 && row_kernel && shape_edge_rows(nT, c->heater_rows, g.ntyE, hmax, ty_in, ty_edge)) {
+    g.tyE = ty_in;
+    g.tyE0 = ty_edge;
+  }
   return g;
 }
 
@@ -156,6 +187,7 @@ KParams make_params(const lbm_config* c, int ncu) {
   P.ntyE = g.ntyE;
   P.txE = g.txE;
   P.tyE = g.tyE;
+  P.tyE0 = g.tyE0;
   P.nblkL = P.ntxL * P.ntyL;
   P.nblkE = P.ntxE * P.ntyE;
   P.tyL = c->precision == LBM_F64 ? TY_F64 : TY_F32;

@@ -50,11 +50,11 @@ __device__ __forceinline__ void energy_rows_tile(
     const KParams& P, RowsShared<NW, B>& sh, const float* __restrict__ Tin, float* __restrict__ Tout,
     const float* __restrict__ rho, const float* __restrict__ uxa, const float* __restrict__ uya,
     double* __restrict__ hist_slot, DevDiag* __restrict__ diag, int sub, double dtd,
-    const long long* __restrict__ dstep_prev, int tile, int x0, int j0) {
+    const long long* __restrict__ dstep_prev, int tile, int x0, int j0, int TY) {
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nx = P.nx, nT = P.nT, nh = P.nh;
-  const int TX = P.txE, TY = P.tyE, H4 = TY + 8;
+  const int TX = P.txE, H4 = TY + 8;
   const int gx = wrapm(x0 - 4 + lane, nx);
   const int r0 = w * B;          // first tile row of this wave's band
   const int jb = j0 - 4 + r0;    // its temperature row
@@ -246,6 +246,15 @@ __device__ __forceinline__ void energy_rows_tile(
   const bool lane_out = lane >= 4 && lane < 4 + TX && x0 + lane - 4 < nx;
   float eS = lT[0], eN = lT[B + 1];  // rows below and above the band
   double Qb = 0.0, Qt = 0.0, Qs = 0.0;
+  // band rows that carry a boundary-flux diagnostic (-1: none in this wave): the bottom
+  // row, the top row under a Dirichlet top, the first fluid row above the heater
+  auto pick = [&](int j) {
+    const int k = j - jb, r = r0 + k;
+    return (k >= 0 && k < B && r >= 4 && r < 4 + TY) ? k : -1;
+  };
+  const int kB = PLAIN ? -1 : pick(0);
+  const int kT = (PLAIN || !top_dirichlet) ? -1 : pick(nT - 1);
+  const int kS = (PLAIN || nh == 0) ? -1 : pick(nh);
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     if constexpr (!PLAIN) {
@@ -260,6 +269,7 @@ __device__ __forceinline__ void energy_rows_tile(
       if (jb + B == nT) eN = top_dirichlet ? Ttop : Y[B - 1];
     }
     const float wgt = (s == 0 || s == 3) ? 1.f : 2.f;
+    float qB = 0.f, qT = 0.f, qS = 0.f;
     if (wave_live) {
       float s0 = eS, sE = lane_east(eS), sW = lane_west(eS);
       float c0 = Y[0], wE = lane_east(c0), wW = lane_west(c0);
@@ -275,12 +285,9 @@ __device__ __forceinline__ void energy_rows_tile(
           h += aP[k] * (nE - sW) + aM[k] * (sE - nW);
           h -= l2[k] * __builtin_amdgcn_sqrtf(Tp);
           if constexpr (!PLAIN) {
-            const int r = r0 + k;
-            if (r >= 4 && r < 4 + TY && lane_out) {
-              if (j == 0) Qb += (double)(wgt * (flux_bottom ? qb : fq0 * (s0 - Tp)));
-              if (j == nT - 1 && top_dirichlet) Qt += (double)(wgt * (fqt * (n0 - Tp)));
-              if (nh > 0 && j == nh) Qs += (double)(wgt * (fqh * (s0 - Tp)));
-            }
+            if (k == kB) qB = flux_bottom ? qb : fq0 * (s0 - Tp);
+            if (k == kT) qT = fqt * (n0 - Tp);
+            if (k == kS) qS = fqh * (s0 - Tp);
           }
           if (s == 0) {
             Y[k] = T0[k] + dt2 * h;
@@ -294,6 +301,11 @@ __device__ __forceinline__ void energy_rows_tile(
         }
         s0 = c0; sE = wE; sW = wW;
         c0 = n0; wE = nE; wW = nW;
+      }
+      if constexpr (!PLAIN) {
+        if (kB >= 0) Qb += (double)(lane_out ? wgt * qB : 0.f);
+        if (kT >= 0) Qt += (double)(lane_out ? wgt * qT : 0.f);
+        if (kS >= 0) Qs += (double)(lane_out ? wgt * qS : 0.f);
       }
     }
     if (s < 3) {
@@ -325,19 +337,26 @@ __device__ __forceinline__ void energy_rows_tile(
   v[3] = Qt * d6;
   v[4] = Qs * d6;
   if (nh == 0) v[4] = v[2];
-  block_sum_n<5, NW>(v, sh.red);
-  if (t == 0) {
-    double* pe = hist_slot + 5 * tile;
-    if (sub == 0) {
+  // interior tiles carry no boundary flux: their partials 2..4 are zero
+  constexpr int KV = PLAIN ? 2 : 5;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) pe[k] = v[k];
-    } else {
-      pe[0] += v[0];
-      pe[1] = v[1];
-      pe[2] += v[2];
-      pe[3] += v[3];
-      pe[4] += v[4];
+  for (int k = 0; k < KV; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < KV; ++k) sh.red[w * KV + k] = v[k];
+  __syncthreads();
+  // lane k of wave 0 sums partial k over the waves in order and stores it
+  if (w == 0 && lane < 5) {
+    double a = 0.0;
+    if (lane < KV) {
+      a = sh.red[lane];
+      for (int q = 1; q < NW; ++q) a += sh.red[q * KV + lane];
     }
+    double* pe = hist_slot + 5 * tile;
+    if (sub == 0) pe[lane] = a;
+    else if (lane == 1) pe[1] = a;
+    else pe[lane] += a;
   }
 }
 
@@ -348,15 +367,17 @@ __device__ __forceinline__ void energy_rows_step(
     double* __restrict__ hist_slot, DevDiag* __restrict__ diag, int sub, double dtd,
     const long long* __restrict__ dstep_prev, int tile) {
   __shared__ RowsShared<NW, B> sh;
-  const int nT = P.nT, TY = P.tyE;
-  const int x0 = (tile % P.ntxE) * P.txE, j0 = (tile / P.ntxE) * TY;
+  const int nT = P.nT;
+  int j0, TY;
+  energy_tile_rows(P, tile, j0, TY);
+  const int x0 = (tile % P.ntxE) * P.txE;
   const bool plain_tile = (j0 - 4 >= P.nh) && (j0 + TY + 3 <= nT - 1);
   if (plain_tile)
     energy_rows_tile<NW, B, true>(P, sh, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
-                                  tile, x0, j0);
+                                  tile, x0, j0, TY);
   else
     energy_rows_tile<NW, B, false>(P, sh, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
-                                   tile, x0, j0);
+                                   tile, x0, j0, TY);
 
 }
 

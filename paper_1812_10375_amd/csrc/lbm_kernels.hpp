@@ -64,6 +64,14 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
   return k * q + (k < r ? k : r) + (b >> 3);
 }
 
+// Temperature-grid rows of energy tile `tile`: the first tile row holds tyE0 rows, the
+// following ones tyE each, and the last one what remains of the nT rows.
+__device__ __forceinline__ void energy_tile_rows(const KParams& P, int tile, int& j0, int& ty) {
+  const int tr = tile / P.ntxE;
+  j0 = tr == 0 ? 0 : P.tyE0 + (tr - 1) * P.tyE;
+  ty = min(tr == 0 ? P.tyE0 : P.tyE, P.nT - j0);
+}
+
 // 1/v: exact for FP64, the hardware reciprocal (1 ulp) for FP32
 template <typename real>
 __device__ __forceinline__ real fast_rcp(real v) {
@@ -680,6 +688,7 @@ __device__ __forceinline__ void energy_lds_tile(
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nx = P.nx, nT = P.nT, nh = P.nh;
+  // uniform tiles here (tyE0 == tyE): the LDS layout is sized for tyE rows
   const int TXr = P.txE, TY = P.tyE, H4 = TY + 8;
   const int x0 = (tile % P.ntxE) * TXr, j0 = (tile / P.ntxE) * TY;
   const int gx = wrapm(x0 - 4 + lane, nx);  // global column of this lane

@@ -16,7 +16,7 @@ struct KParams {
   int nx, ny, nh, nT;
   int flags, top_bc, bottom_tbc, top_tbc;
   int ntxL, ntyL, nblkL, tyL;
-  int ntxE, ntyE, nblkE, tyE, txE, pad1;
+  int ntxE, ntyE, nblkE, tyE, txE, tyE0;  // energy tiles: first tile row tyE0 rows, then tyE
   // equation of state (FP64)
   double a, b, R, G, Tc, inv_Tc, kappa, phi_sat, T_sat, inv3, two_G;
   // collision
