@@ -44,7 +44,8 @@ struct RowsShared {
 };
 
 // The tile work.  PLAIN: every row of the tile (halo included) is a fluid row away from
-// both boundaries, so no row needs boundary handling and none is skipped.
+// both boundaries, so no row needs boundary handling and none is skipped, and advection
+// and the latent term are both on.
 template <int NW, int B, bool PLAIN>
 __device__ __forceinline__ void energy_rows_tile(
     const KParams& P, RowsShared<NW, B>& sh, const float* __restrict__ Tin, float* __restrict__ Tout,
@@ -71,16 +72,20 @@ __device__ __forceinline__ void energy_rows_tile(
   if constexpr (PLAIN) {
     // rows outside the tile are clamped into the fluid rows; their values are unused.  A
     // wave whose band lies wholly beyond the tile loads nothing.
+    if (wave_live) {
 #pragma unroll
-    for (int q = 0; q < B + 2; ++q) {
-      const int j = min(max(jb - 1 + q, nh), nT - 1);
-      lT[q] = 0.f; lR[q] = 1.f; lU[q] = 0.f; lV[q] = 0.f;
-      if (wave_live) {
+      for (int q = 0; q < B + 2; ++q) {
+        const int j = min(max(jb - 1 + q, nh), nT - 1);
         lT[q] = ld32(Tin, (unsigned)j * (unsigned)nx + gx);
         const unsigned n = (unsigned)(j - nh) * (unsigned)nx + gx;
         lR[q] = ld32(rho, n);
         lU[q] = ld32(uxa, n);
         lV[q] = ld32(uya, n);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < B + 2; ++q) {
+        lT[q] = 0.f; lR[q] = 1.f; lU[q] = 0.f; lV[q] = 0.f;
       }
     }
   } else {
@@ -141,21 +146,15 @@ __device__ __forceinline__ void energy_rows_tile(
       const float iE = __builtin_amdgcn_rcpf(r + rE);
       const float ge = k2 * rE * iE, gw = k2 * rWv * lane_west(iE);
       const float gn = k2 * lR[q + 1] * rN[q], gs = k2 * lR[q - 1] * rN[q - 1];
-      float ax = 0.f, ay = 0.f, l1 = 0.f;
-      aP[k] = 0.f; aM[k] = 0.f; l2[k] = 0.f;
+      // advection and latent heat are both on in plain tiles
       const float ux = lU[q], uy = lV[q];
-      if (do_adv) {
-        ax = -ux * inv3;
-        ay = -uy * inv3;
-        aP[k] = -(ux + uy) * inv12;
-        aM[k] = -(ux - uy) * inv12;
-      }
-      if (do_lat) {
-        const float br = bb * r, d1 = 1.f - br, d2 = 1.f + 2.f * br - br * br;
-        const float dv = divu(q) * __builtin_amdgcn_rcpf(d1 * d2);
-        l1 = dv * (g1a * d2 - g1b * r * d1);
-        l2[k] = dv * (g2a * r * d1);
-      }
+      const float ax = -ux * inv3, ay = -uy * inv3;
+      aP[k] = -(ux + uy) * inv12;
+      aM[k] = -(ux - uy) * inv12;
+      const float br = bb * r, d1 = 1.f - br, d2 = 1.f + 2.f * br - br * br;
+      const float dv = divu(q) * __builtin_amdgcn_rcpf(d1 * d2);
+      const float l1 = dv * (g1a * d2 - g1b * r * d1);
+      l2[k] = dv * (g2a * r * d1);
       cE[k] = ge + ax;
       cW[k] = gw - ax;
       cN[k] = gn + ay;
@@ -371,7 +370,8 @@ __device__ __forceinline__ void energy_rows_step(
   int j0, TY;
   energy_tile_rows(P, tile, j0, TY);
   const int x0 = (tile % P.ntxE) * P.txE;
-  const bool plain_tile = (j0 - 4 >= P.nh) && (j0 + TY + 3 <= nT - 1);
+  const bool plain_tile = (j0 - 4 >= P.nh) && (j0 + TY + 3 <= nT - 1) &&
+                          !(P.flags & (NO_ADVECTION | NO_LATENT));
   if (plain_tile)
     energy_rows_tile<NW, B, true>(P, sh, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
                                   tile, x0, j0, TY);
