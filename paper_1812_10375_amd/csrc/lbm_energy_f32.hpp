@@ -339,7 +339,7 @@ __device__ __forceinline__ void energy_rows_tile(
   // interior tiles carry no boundary flux: their partials 2..4 are zero
   constexpr int KV = PLAIN ? 2 : 5;
 #pragma unroll
-  for (int k = 0; k < KV; ++k) v[k] = wave_sum(v[k]);
+  for (int k = 0; k < KV; ++k) v[k] = wave_sum_dpp(v[k]);
   __syncthreads();
   if (lane == 0)
 #pragma unroll

@@ -104,6 +104,46 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
+// One DPP move of a double (both halves): the value of the lane that `CTRL` selects, 0
+// where there is none or where `ROWS` leaves the row out.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROWS, 0xf, true);
+  const unsigned hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWS, 0xf, true);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes in a fixed order without LDS: running sums within each row of
+// 16 lanes (shifts by 1, 2, 4, 8), then the row totals carried by row_bcast:15 into rows
+// 1 and 3 and row_bcast:31 into rows 2 and 3.  Lane 63 ends with the total, which every
+// lane receives.
+__device__ __forceinline__ double lane63_f64(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)u, 63);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0x111, 0xf>(v);
+  v += dpp_f64<0x112, 0xf>(v);
+  v += dpp_f64<0x114, 0xf>(v);
+  v += dpp_f64<0x118, 0xf>(v);
+  v += dpp_f64<0x142, 0xa>(v);
+  v += dpp_f64<0x143, 0xc>(v);
+  return lane63_f64(v);
+}
+// The same for the maximum of values >= 0 (the lanes without a source read 0).
+__device__ __forceinline__ double wave_max_dpp(double v) {
+  v = fmax(v, dpp_f64<0x111, 0xf>(v));
+  v = fmax(v, dpp_f64<0x112, 0xf>(v));
+  v = fmax(v, dpp_f64<0x114, 0xf>(v));
+  v = fmax(v, dpp_f64<0x118, 0xf>(v));
+  v = fmax(v, dpp_f64<0x142, 0xa>(v));
+  v = fmax(v, dpp_f64<0x143, 0xc>(v));
+  return lane63_f64(v);
+}
+
 // Block-wide sums over NW waves of K doubles (K*NW <= 96 doubles of scratch).
 template <int K, int NW>
 __device__ __forceinline__ void block_sum_n(double (&v)[K], double* red) {
@@ -632,10 +672,33 @@ __device__ __forceinline__ void collide_tile(
   }
   if (err) flag_error(diag, err, step);
   double v[2] = {mass, uyrow};
-  double vm = wave_max((double)umax2);
-  __syncthreads();
-  if (lane == 0) red[96 + wv] = vm;
-  block_sum_n<2, NT / 64>(v, red);
+  if constexpr (sizeof(real) == 4) {
+    // FP32 path: register-only wave reductions, then the waves in order
+    const double vm = wave_max_dpp((double)umax2);
+    v[0] = wave_sum_dpp(v[0]);
+    v[1] = wave_sum_dpp(v[1]);
+    __syncthreads();
+    if (lane == 0) {
+      red[96 + wv] = vm;
+      red[2 * wv] = v[0];
+      red[2 * wv + 1] = v[1];
+    }
+    __syncthreads();
+    if (t == 0) {
+      double a = red[0], b = red[1];
+      for (int q = 1; q < NT / 64; ++q) {
+        a += red[2 * q];
+        b += red[2 * q + 1];
+      }
+      v[0] = a;
+      v[1] = b;
+    }
+  } else {
+    double vm = wave_max((double)umax2);
+    __syncthreads();
+    if (lane == 0) red[96 + wv] = vm;
+    block_sum_n<2, NT / 64>(v, red);
+  }
   if (t == 0) {
     partL_out[3 * tile] = v[0];
     partL_out[3 * tile + 1] = fmax(fmax(red[96], red[97]), fmax(red[98], red[99]));
