@@ -92,7 +92,9 @@ __device__ __forceinline__ void energy_rows_tile(
 #pragma unroll
     for (int q = 0; q < B + 2; ++q) {
       const int j = jb - 1 + q;
-      lT[q] = 0.f; lR[q] = 0.f; lU[q] = 0.f; lV[q] = 0.f;
+      // rows that are not loaded keep finite values: they are computed with the others,
+      // and their results reach only halo or ghost rows
+      lT[q] = 0.f; lR[q] = 1.f; lU[q] = 0.f; lV[q] = 0.f;
       if (r0 - 1 + q >= H4) continue;
       if (j >= 0 && j < nT) {
         lT[q] = Tin[(size_t)j * nx + gx];
@@ -254,15 +256,20 @@ __device__ __forceinline__ void energy_rows_tile(
   const int kB = PLAIN ? -1 : pick(0);
   const int kT = (PLAIN || !top_dirichlet) ? -1 : pick(nT - 1);
   const int kS = (PLAIN || nh == 0) ? -1 : pick(nh);
+  // band rows of the ghost rows below the bottom and above the top (-1: none)
+  const int kGb = (!PLAIN && jb <= -1 && -1 < jb + B) ? -1 - jb : -1;
+  const int kGt = (!PLAIN && jb <= nT && nT < jb + B) ? nT - jb : -1;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     if constexpr (!PLAIN) {
-      // ghost rows take their stage value from the row next to them
+      // ghost rows take their stage value from the row next to them (only the waves
+      // whose band holds a ghost row)
+      if (kGb >= 0 || kGt >= 0) {
 #pragma unroll
-      for (int k = 0; k < B; ++k) {
-        const int j = jb + k;
-        if (j == -1) Y[k] = flux_bottom ? ((k + 1 < B ? Y[k + 1] : eN) + gq) : Tbot;
-        if (j == nT) Y[k] = top_dirichlet ? Ttop : (k > 0 ? Y[k - 1] : eS);
+        for (int k = 0; k < B; ++k) {
+          if (k == kGb) Y[k] = flux_bottom ? ((k + 1 < B ? Y[k + 1] : eN) + gq) : Tbot;
+          if (k == kGt) Y[k] = top_dirichlet ? Ttop : (k > 0 ? Y[k - 1] : eS);
+        }
       }
       if (jb == 0) eS = flux_bottom ? Y[0] + gq : Tbot;
       if (jb + B == nT) eN = top_dirichlet ? Ttop : Y[B - 1];
@@ -276,9 +283,7 @@ __device__ __forceinline__ void energy_rows_tile(
       for (int k = 0; k < B; ++k) {
         const float n0 = (k + 1 < B) ? Y[k + 1] : eN;
         const float nE = lane_east(n0), nW = lane_west(n0);
-        const int j = jb + k;
-        const bool active = PLAIN || ((r0 + k < H4) && j >= 0 && j < nT);
-        if (active) {
+        {
           const float Tp = c0;
           float h = cP[k] * Tp + cE[k] * wE + cW[k] * wW + cN[k] * n0 + cS[k] * s0;
           h += aP[k] * (nE - sW) + aM[k] * (sE - nW);
