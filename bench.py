@@ -114,6 +114,29 @@ def batched(steps=200, warmup=20):
            "MLUPS": nodes * steps / (ms * 1e-3) / 1e6, "tile_rows": rows,
            "autotune_ms_per_step": tuned_ms, "status": max(abs(o["status"]) for o in obs)}
     bat.close()
+    # the same steps captured once in a HIP graph (one diagnostics-history period) and
+    # replayed: the first replay warms up, the second is timed
+    hist = 256
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    bat = BatchLattice(scs, stream=s)
+    bat.observe()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bat.step(hist)
+    with torch.cuda.stream(s):
+        g.replay()
+    torch.cuda.synchronize()
+    e0.record(s)
+    with torch.cuda.stream(s):
+        g.replay()
+    e1.record(s)
+    torch.cuda.synchronize()
+    gms = e0.elapsed_time(e1)
+    obs = bat.observe(check=False)
+    out["graph"] = {"steps": hist, "ms_per_step": gms / hist, "MLUPS": nodes * hist / (gms * 1e-3) / 1e6,
+                    "status": max(abs(o["status"]) for o in obs)}
+    bat.close()
     return out
 
 
