@@ -23,15 +23,16 @@
 //   steps     HIST x 5      per-step totals of hist
 //   diag      DevDiag       FP64 diagnostics
 //
-// Per step two kernels run: k_collide (moments, EOS, forces, MRT collision) and
-// k_energy (all four RK4 stages of the temperature equation on an LDS tile with a
-// four-cell halo).  The mass for rho_ave (Eq. 9) follows from continuity: streaming and
-// bounce-back move populations and the collision conserves their sum, so only the open
-// top changes it; every collide block adds the previous step's net inflow (same values,
-// same order) to the stored mass.  The energy kernel's top tiles apply the outlet rule
-// to their own columns and record their net inflow; the energy
-// diagnostics are reduced in step order later by k_reduce_steps / k_finish.  No
-// atomics touch the diagnostics, so reruns are bitwise identical.
+// Per step two kernels run: k_collide (moments, EOS, forces, MRT collision) and the
+// energy update (all four RK4 stages of the temperature equation on a tile with a
+// four-cell halo: k_energy_rows in FP32, k_energy in FP64 and for the isotropic scheme).
+// The mass for rho_ave (Eq. 9) follows from continuity: streaming and bounce-back move
+// populations and the collision conserves their sum, so only the open top changes it;
+// every collide block adds the previous step's net inflow (same values, same order) to
+// the stored mass.  Block 0 of the energy launch applies the outlet rule to every top
+// column and records the net inflow per tile column; the energy diagnostics are reduced
+// in step order later by k_reduce_steps / k_finish.  No atomics touch the diagnostics,
+// so reruns are bitwise identical.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -662,7 +663,7 @@ __device__ __forceinline__ void collide_tile(
     ux_out[n] = ux;
     uy_out[n] = uy;
     // post-collision mass (per node in the field precision, accumulated in FP64); the
-    // open top's net exchange is added by the energy kernel's top tiles
+    // open top's net exchange is added by the outlet block of the energy launch
     const real ms = ((f[k][0] + f[k][1]) + (f[k][2] + f[k][3])) + ((f[k][4] + f[k][5]) + (f[k][6] + f[k][7])) + f[k][8];
     mass += (double)ms;
     const real u2 = ux * ux + uy * uy;

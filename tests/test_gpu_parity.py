@@ -172,6 +172,16 @@ def test_fp32_tall_domain_with_interior_tiles():
     _check32_heat(sc, 300)
 
 
+@pytest.mark.parametrize("nx,ny,nh,rows", [(128, 256, 25, 44), (96, 300, 12, 40)])
+def test_fp32_shaped_edge_tile_rows(nx, ny, nh, rows):
+    # with these heights the FP32 energy grid shortens its first and last tile rows
+    # (first 31 or 30 rows, interior 44 or 42, last 30), so tiles of three heights and
+    # both code paths meet at the tile-row seams
+    sc = S.pool_boiling(nx=nx, ny=ny, heater_rows=nh, n_sites=2, min_spacing=32, seed=5)
+    sc["tile_rows"] = rows
+    _check32_heat(sc, 1000)
+
+
 def test_fp32_energy_substeps_and_flux_bottom():
     sc = S.film_evaporation(nx=40, ny=30, film=10, seed=3, precision="f32")
     sc["n_sub"] = 3
