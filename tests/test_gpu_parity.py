@@ -151,6 +151,13 @@ def test_fp32_pool_boiling_full_size_first_steps():
     _check32(sc, 20)
 
 
+def test_fp32_pool_boiling_4096_first_steps():
+    # the 4096 x 4096 + 25 workload the benchmark times for HBM-resident rates: many
+    # rounds of energy workgroups and 67 MB field planes
+    sc = S.pool_boiling(nx=4096, ny=4096)
+    _check32(sc, 3)
+
+
 def _check32_heat(sc, steps, rel=1e-3):
     res, e = _check32(sc, steps)
     og, oo = res["gpu_obs"], res["orc_obs"]
