@@ -55,6 +55,29 @@ def test_batch_domains_evolve_as_they_do_alone(prec):
         one.close()
 
 
+def test_batch_with_shortened_edge_tile_rows():
+    # FP32 domains whose energy grids shorten their first and last tile rows (each its
+    # own heights) next to a uniform one, in one batch: each evolves as it does alone
+    from paper_1812_10375_amd.lbm import BatchLattice, Lattice
+    scs = [S.pool_boiling(nx=128, ny=256, heater_rows=25, n_sites=2, min_spacing=32, seed=5),
+           S.pool_boiling(nx=96, ny=300, heater_rows=12, n_sites=2, min_spacing=32, seed=6, superheat=0.2),
+           S.film_evaporation(nx=70, ny=50, film=12, superheat=0.05, seed=22, precision="f32")]
+    for sc, rows in zip(scs, (44, 40, 16)):
+        sc["tile_rows"] = rows
+    bat = BatchLattice(scs)
+    bat.step(200)
+    bobs = bat.observe()
+    for i, sc in enumerate(scs):
+        one = Lattice(sc)
+        one.step(200)
+        oobs = one.observe()
+        for k in ("rho", "T"):
+            assert np.array_equal(bat.read(i, k), one.read(k)), (i, k)
+        assert bobs[i]["energy"] == oobs["energy"], i
+        one.close()
+    bat.close()
+
+
 def test_batch_domain_against_the_oracle():
     from oracle.lbm import OracleSim
     from paper_1812_10375_amd.lbm import BatchLattice
