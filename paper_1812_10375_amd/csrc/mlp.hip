@@ -107,6 +107,47 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const Gemm g) {
   }
 }
 
+// The weight-gradient products contract over the batch (K = B rows) into few output
+// tiles.  Here the 16 waves of a block share one 16 x 16 tile: wave w takes the k-steps
+// w, w + 16, ... of 32, and lane l of wave 0 adds the 16 partial tiles in wave order.
+constexpr int SK_WAVES = 16;
+__global__ void __launch_bounds__(SK_WAVES * 64) k_gemm_bf16_splitk(const Gemm g) {
+  __shared__ f32x4 part[SK_WAVES][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int z = blockIdx.y;
+  const int tn = (g.N + 15) / 16;
+  const int tile = blockIdx.x;
+  const int m0 = (tile / tn) * 16, n0 = (tile % tn) * 16;
+  const int i = lane & 15, kq = lane >> 4;
+  const __bf16* A = g.A + z * g.saz;
+  const __bf16* B = g.B + z * g.sbz;
+  const bool row_ok = m0 + i < g.M, col_ok = n0 + i < g.N;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 32 * wave; k0 < g.K; k0 += 32 * SK_WAVES) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + 8 * kq + e;
+      const bool k_ok = k < g.K;
+      a[e] = (row_ok && k_ok) ? A[(long)(m0 + i) * g.sam + (long)k * g.sak] : (__bf16)0.f;
+      b[e] = (col_ok && k_ok) ? B[(long)k * g.sbk + (long)(n0 + i) * g.sbn] : (__bf16)0.f;
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (wave != 0) return;
+  f32x4 t = part[0][lane];
+  for (int q = 1; q < SK_WAVES; ++q) t += part[q][lane];
+  const int n = n0 + i;
+  if (n >= g.N) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int m = m0 + 4 * kq + r;
+    if (m < g.M) g.Cf[(long)m * g.ldc + n + z * g.scf] = t[r];
+  }
+}
+
 // inputs [B][4] FP32 (member z at x + z * sx) -> [B][32] BF16 (member z at xb + z * sxb),
 // zero beyond column 4; blockIdx.y = member
 __global__ void k_prep_x(const float* __restrict__ x, long sx, __bf16* __restrict__ xb, long sxb, int B) {
@@ -120,14 +161,15 @@ __global__ void k_prep_x(const float* __restrict__ x, long sx, __bf16* __restric
 
 // dY = 2 (Y - T) / B on the 2 outputs (zero on the padded columns), and the loss of
 // each member: one block per member, fixed-order reduction.
-__global__ void __launch_bounds__(256) k_out_grad(const float* __restrict__ Y, const float* __restrict__ T, long st,
+constexpr int OG_THREADS = 1024;
+__global__ void __launch_bounds__(OG_THREADS) k_out_grad(const float* __restrict__ Y, const float* __restrict__ T, long st,
                                                    int B, float* __restrict__ dYf, __bf16* __restrict__ dYb,
                                                    float* __restrict__ loss, long sy, long sd) {
-  __shared__ float red[256];
+  __shared__ float red[OG_THREADS];
   const int z = blockIdx.x;
   const float inv = 1.f / (float)B;
   float acc = 0.f;
-  for (long t = threadIdx.x; t < (long)B * NP3; t += 256) {
+  for (long t = threadIdx.x; t < (long)B * NP3; t += OG_THREADS) {
     const long b = t / NP3;
     const int c = (int)(t % NP3);
     float d = 0.f;
@@ -141,21 +183,32 @@ __global__ void __launch_bounds__(256) k_out_grad(const float* __restrict__ Y, c
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = OG_THREADS / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) loss[z] = red[0] * inv;
 }
 
-// db[n] = sum over rows of D[row][n] (n < N, row < B), per member; fixed order
-__global__ void k_colsum(const float* __restrict__ D, int B, int N, long sdz, float* __restrict__ db, long sbz) {
-  const int z = blockIdx.y;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// db[n] = sum over rows of D[row][n] (n < N, row < B), per member, in a fixed order: a
+// block of 1024 threads covers 16 columns; thread (g, c) sums rows g, g + 64, ... of
+// column c in order, and the 64 row-group partials are then added pairwise in LDS.
+constexpr int CS_THREADS = 1024, CS_COLS = 16, CS_GROUPS = CS_THREADS / CS_COLS;
+__global__ void __launch_bounds__(CS_THREADS) k_colsum(const float* __restrict__ D, int B, int N, long sdz,
+                                                       float* __restrict__ db, long sbz) {
+  __shared__ float part[CS_GROUPS][CS_COLS];
+  const int z = blockIdx.y, c = threadIdx.x % CS_COLS, grp = threadIdx.x / CS_COLS;
+  const int n = blockIdx.x * CS_COLS + c;
   float s = 0.f;
-  for (int b = 0; b < B; ++b) s += D[z * sdz + (long)b * N + n];
-  db[z * sbz + n] = s;
+  if (n < N)
+    for (int b = grp; b < B; b += CS_GROUPS) s += D[z * sdz + (long)b * N + n];
+  part[grp][c] = s;
+  __syncthreads();
+  for (int h = CS_GROUPS / 2; h > 0; h >>= 1) {
+    if (grp < h) part[grp][c] += part[grp + h][c];
+    __syncthreads();
+  }
+  if (grp == 0 && n < N) db[z * sbz + n] = part[0][c];
 }
 
 __global__ void k_to_bf16(const float* __restrict__ w, __bf16* __restrict__ wb, long n) {
@@ -235,7 +288,10 @@ int hip_rc(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 template <int EPI>
 void gemm(lbm_mlp* m, const Gemm& g) {
   const int tiles = ((g.M + 15) / 16) * ((g.N + 15) / 16);
-  hipLaunchKernelGGL(k_gemm_bf16<EPI>, dim3((tiles + 3) / 4, m->members), dim3(256), 0, m->stream, g);
+  if (EPI == EPI_F32 && g.K >= 32 * SK_WAVES)  // long contraction into few tiles: split it
+    hipLaunchKernelGGL(k_gemm_bf16_splitk, dim3(tiles, m->members), dim3(SK_WAVES * 64), 0, m->stream, g);
+  else
+    hipLaunchKernelGGL(k_gemm_bf16<EPI>, dim3((tiles + 3) / 4, m->members), dim3(256), 0, m->stream, g);
 }
 
 Gemm blank() {
@@ -401,7 +457,7 @@ int lbm_mlp_backward(lbm_mlp* m, const float* d_x, const float* d_t, int B, int 
   float* Y = m->at<float>(L.y);
   const long sx = per_member ? (long)B * IN : 0, st = per_member ? (long)B * OUT : 0;
   forward(m, d_x, sx, B, Y, A * OUT);
-  hipLaunchKernelGGL(k_out_grad, dim3(m->members), dim3(256), 0, m->stream, Y, d_t, st, B, m->at<float>(L.dyf),
+  hipLaunchKernelGGL(k_out_grad, dim3(m->members), dim3(OG_THREADS), 0, m->stream, Y, d_t, st, B, m->at<float>(L.dyf),
                      m->at<__bf16>(L.dyb), d_loss, A * OUT, A * NP3);
   float* gr = m->at<float>(L.g);
   const __bf16* wb = m->at<__bf16>(L.wb);
@@ -412,7 +468,7 @@ int lbm_mlp_backward(lbm_mlp* m, const float* d_x, const float* d_t, int B, int 
   g.M = H; g.N = NP3; g.K = B;
   g.Cf = gr + OFF_W3; g.ldc = NP3; g.scf = PP;
   gemm<EPI_F32>(m, g);
-  hipLaunchKernelGGL(k_colsum, dim3(1, m->members), dim3(NP3), 0, m->stream, m->at<float>(L.dyf), B, NP3,
+  hipLaunchKernelGGL(k_colsum, dim3((NP3 + CS_COLS - 1) / CS_COLS, m->members), dim3(CS_THREADS), 0, m->stream, m->at<float>(L.dyf), B, NP3,
                      A * NP3, gr + OFF_B3, (long)PP);
   // dZ2 = (dY W3^T) * gelu'(Z2)
   g = blank();
@@ -430,7 +486,7 @@ int lbm_mlp_backward(lbm_mlp* m, const float* d_x, const float* d_t, int B, int 
   g.M = H; g.N = H; g.K = B;
   g.Cf = gr + OFF_W2; g.ldc = H; g.scf = PP;
   gemm<EPI_F32>(m, g);
-  hipLaunchKernelGGL(k_colsum, dim3(1, m->members), dim3(H), 0, m->stream, m->at<float>(L.d2f), B, H, A * H,
+  hipLaunchKernelGGL(k_colsum, dim3((H + CS_COLS - 1) / CS_COLS, m->members), dim3(CS_THREADS), 0, m->stream, m->at<float>(L.d2f), B, H, A * H,
                      gr + OFF_B2, (long)PP);
   // dZ1 = (dZ2 W2^T) * gelu'(Z1)
   g = blank();
@@ -448,7 +504,7 @@ int lbm_mlp_backward(lbm_mlp* m, const float* d_x, const float* d_t, int B, int 
   g.M = KP1; g.N = H; g.K = B;
   g.Cf = gr + OFF_W1; g.ldc = H; g.scf = PP;
   gemm<EPI_F32>(m, g);
-  hipLaunchKernelGGL(k_colsum, dim3(1, m->members), dim3(H), 0, m->stream, m->at<float>(L.d1f), B, H, A * H,
+  hipLaunchKernelGGL(k_colsum, dim3((H + CS_COLS - 1) / CS_COLS, m->members), dim3(CS_THREADS), 0, m->stream, m->at<float>(L.d1f), B, H, A * H,
                      gr + OFF_B1, (long)PP);
   return hip_rc(hipGetLastError());
 }
