@@ -335,12 +335,10 @@ int lbm_set_stream(lbm_ctx* h, void* hip_stream) {
   return LBM_OK;
 }
 
-int lbm_observe(lbm_ctx* h, lbm_obs* out) {
-  if (!h || !out) return LBM_EINVAL;
+// Copies the folded diagnostics of h to the host (synchronises the stream).
+static int read_observation(lbm_ctx* h, lbm_obs* out) {
   const Layout& L = h->L;
   DevDiag* dd = h->at<DevDiag>(L.diag);
-  if (h->cfg.precision == LBM_F64) finish_reductions<double>(h);
-  else finish_reductions<float>(h);
   DevDiag d;
   long long dstep = 0;
   // the device's step counter is authoritative: graph replays advance it without the host
@@ -372,6 +370,13 @@ int lbm_observe(lbm_ctx* h, lbm_obs* out) {
     return LBM_ENONFINITE;
   }
   return LBM_OK;
+}
+
+int lbm_observe(lbm_ctx* h, lbm_obs* out) {
+  if (!h || !out) return LBM_EINVAL;
+  if (h->cfg.precision == LBM_F64) finish_reductions<double>(h);
+  else finish_reductions<float>(h);
+  return read_observation(h, out);
 }
 
 int lbm_read_field(lbm_ctx* h, int field, void* dst, size_t bytes, int dst_is_device) {
@@ -587,9 +592,12 @@ int lbm_batch_set_stream(lbm_batch* b, void* hip_stream) {
 int lbm_batch_observe(lbm_batch* b, lbm_obs* out) {
   if (!b || !out) return LBM_EINVAL;
   int status = LBM_OK;
-  // every domain folds its history now, so the shared history slot stays common
+  // every domain folds its history now (two launches for the whole batch), so the
+  // shared history slot stays common
+  if (b->dom[0]->cfg.precision == LBM_F64) batch_finish_reductions<double>(b);
+  else batch_finish_reductions<float>(b);
   for (size_t i = 0; i < b->dom.size(); ++i) {
-    const int rc = lbm_observe(b->dom[i], &out[i]);
+    const int rc = read_observation(b->dom[i], &out[i]);
     if (rc == LBM_ENONFINITE) status = LBM_ENONFINITE;
     else if (rc) return rc;
   }

@@ -98,4 +98,24 @@ __global__ void __launch_bounds__(NW * 64)
       sub, dtd, reinterpret_cast<const long long*>(ws + L.dstep[1 - cur]), g - D.tile0E);
 }
 
+// The history fold for every domain of a batch at once: blockIdx.y = domain,
+// blockIdx.x = history slot (all domains share the slots, the step and the parity).
+template <typename real>
+__global__ void __launch_bounds__(NT)
+    k_reduce_steps_batch(const DomainDev* __restrict__ tab, int first, int hist_cap) {
+  const DomainDev& D = tab[blockIdx.y];
+  reduce_steps_block(D.P, reinterpret_cast<const double*>(D.ws + D.L.hist), reinterpret_cast<double*>(D.ws + D.L.steps),
+                     first, hist_cap, blockIdx.x);
+}
+
+template <typename real>
+__global__ void __launch_bounds__(NT)
+    k_finish_batch(const DomainDev* __restrict__ tab, int first, int count, int hist_cap, int last) {
+  const DomainDev& D = tab[blockIdx.x];
+  char* ws = D.ws;
+  finish_block(D.P, reinterpret_cast<const double*>(ws + D.L.steps), first, count, hist_cap,
+               reinterpret_cast<const double*>(ws + D.L.partL[last]), reinterpret_cast<const double*>(ws + D.L.pmin[last]),
+               reinterpret_cast<DevDiag*>(ws + D.L.diag));
+}
+
 }  // namespace lbmk

@@ -76,4 +76,5 @@ template <typename T> void gather_populations(lbm_ctx* h, T* out);
 template <typename T> int init_fields(lbm_ctx* h, const double* rho0, const double* T0,
                                       const double* gw);
 template <typename T> void batch_step_once(lbm_batch* b);
+template <typename T> void batch_finish_reductions(lbm_batch* b);  // fold every domain's pending steps
 }  // namespace lbmh

@@ -1169,12 +1169,11 @@ __global__ void __launch_bounds__(NT)
 // Per-step totals of the energy partials: block b sums history slot (first + b) % hist
 // over the energy tiles in tile order.  (Templated on the field type only so that each
 // precision's translation unit has its own copy.)
-template <typename real>
-__global__ void __launch_bounds__(NT)
-    k_reduce_steps(const KParams P, const double* __restrict__ hist, double* __restrict__ steps,
-                   int first, int hist_cap) {
+// Per-step totals of the per-tile energy partials (one block per history slot).
+__device__ __forceinline__ void reduce_steps_block(const KParams& P, const double* __restrict__ hist,
+                                                   double* __restrict__ steps, int first, int hist_cap, int s) {
   __shared__ double red[RED_SIZE];
-  const int slot = (first + blockIdx.x) % hist_cap;
+  const int slot = (first + s) % hist_cap;
   const double* h = hist + (size_t)slot * P.nblkE * 5;
   double v[5] = {0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < P.nblkE; b += NT)
@@ -1186,33 +1185,47 @@ __global__ void __launch_bounds__(NT)
     for (int k = 0; k < 5; ++k) steps[5 * slot + k] = v[k];
 }
 
+template <typename real>
+__global__ void __launch_bounds__(NT)
+    k_reduce_steps(const KParams P, const double* __restrict__ hist, double* __restrict__ steps,
+                   int first, int hist_cap) {
+  reduce_steps_block(P, hist, steps, first, hist_cap, blockIdx.x);
+}
+
 // Fold `count` reduced steps into the cumulative diagnostics in step order (running
 // mean / variance of the bottom heat flux by Welford's update), then the mass, rho_ave
 // and max speed of the current state from the last collide partials.
-template <typename real>
-__global__ void __launch_bounds__(NT)
-    k_finish(const KParams P, const double* __restrict__ steps, int first, int count, int hist_cap,
-             const double* __restrict__ partL_last, const double* __restrict__ pmin_last,
-             DevDiag* __restrict__ diag) {
+// Folds `count` per-step totals into the diagnostics in step order (running Welford
+// statistics of the bottom flux) and recomputes mass, rho_ave and the maximum speed of
+// the current state (one block).
+__device__ __forceinline__ void finish_block(const KParams& P, const double* __restrict__ steps, int first,
+                                             int count, int hist_cap, const double* __restrict__ partL_last,
+                                             const double* __restrict__ pmin_last, DevDiag* __restrict__ diag) {
   __shared__ double red[RED_SIZE];
   const int t = threadIdx.x;
-  if (t == 0) {
-    DevDiag& d = *diag;
+  if (t == 0 && count > 0) {
+    // the running values stay in registers through the loop
+    DevDiag& dg = *diag;
+    double dE = dg.dE_cum, en = dg.energy, Qb = dg.Q_bottom_cum, Qt = dg.Q_top_cum, Qs = dg.Q_surface_cum;
+    double qb = dg.q_bottom, qs = dg.q_surface, qm = dg.q_mean, m2 = dg.q_m2;
+    long long nr = dg.nred;
     for (int c = 0; c < count; ++c) {
       const double* v = steps + 5 * ((first + c) % hist_cap);
-      d.dE_cum += v[0];
-      d.energy = v[1];
-      d.Q_bottom_cum += v[2];
-      d.Q_top_cum += v[3];
-      d.Q_surface_cum += v[4];
-      d.q_bottom = v[2] / P.nx;
-      d.q_surface = v[4] / P.nx;
-      d.nred += 1;
-      const double cnt = (double)d.nred, q = d.q_bottom;
-      const double dl = q - d.q_mean;
-      d.q_mean += dl / cnt;
-      d.q_m2 += dl * (q - d.q_mean);
+      dE += v[0];
+      en = v[1];
+      Qb += v[2];
+      Qt += v[3];
+      Qs += v[4];
+      qb = v[2] / P.nx;
+      qs = v[4] / P.nx;
+      nr += 1;
+      const double cnt = (double)nr, q = qb;
+      const double dl = q - qm;
+      qm += dl / cnt;
+      m2 += dl * (q - qm);
     }
+    dg.dE_cum = dE; dg.energy = en; dg.Q_bottom_cum = Qb; dg.Q_top_cum = Qt; dg.Q_surface_cum = Qs;
+    dg.q_bottom = qb; dg.q_surface = qs; dg.q_mean = qm; dg.q_m2 = m2; dg.nred = nr;
   }
   double mv[1] = {0.0};
   double vm = 0.0;
@@ -1230,6 +1243,14 @@ __global__ void __launch_bounds__(NT)
     diag->rho_ave = mv[0] / ((double)P.nx * (double)P.ny);
     diag->max_speed = sqrt(fmax(fmax(red[96], red[97]), fmax(red[98], red[99])));
   }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(NT)
+    k_finish(const KParams P, const double* __restrict__ steps, int first, int count, int hist_cap,
+             const double* __restrict__ partL_last, const double* __restrict__ pmin_last,
+             DevDiag* __restrict__ diag) {
+  finish_block(P, steps, first, count, hist_cap, partL_last, pmin_last, diag);
 }
 
 template <typename real>

@@ -88,6 +88,24 @@ void step_once(lbm_ctx* h) {
 // One step of every domain of a batch: the batched collide kernel, then the batched
 // energy kernel once per energy sub-step.  All domains share the parity, the buffer
 // indices and the history slot; the per-domain host bookkeeping advances together.
+// finish_reductions for every domain of a batch in two launches (the domains share
+// the history slots, the step and the parity)
+template <typename real>
+void batch_finish_reductions(lbm_batch* b) {
+  lbm_ctx* h0 = b->dom[0];
+  const int n = (int)b->dom.size();
+  const int last = (int)((h0->step + 1) & 1);
+  if (h0->hist_count > 0)
+    hipLaunchKernelGGL(lbmk::k_reduce_steps_batch<real>, dim3(h0->hist_count, n), dim3(NT), 0, b->stream, b->table,
+                       h0->hist_first, HIST);
+  hipLaunchKernelGGL(lbmk::k_finish_batch<real>, dim3(n), dim3(NT), 0, b->stream, b->table, h0->hist_first,
+                     h0->hist_count, HIST, last);
+  for (lbm_ctx* h : b->dom) {
+    h->hist_first = (h->hist_first + h->hist_count) % HIST;
+    h->hist_count = 0;
+  }
+}
+
 template <typename real>
 void batch_step_once(lbm_batch* b) {
   lbm_ctx* h0 = b->dom[0];
@@ -117,9 +135,11 @@ void batch_step_once(lbm_batch* b) {
     h->hist_count += 1;
     h->fcur = 1 - fcur;
     h->step += 1;
-    if (h->hist_count == HIST) finish_reductions<real>(h);
   }
+  if (h0->hist_count == HIST) batch_finish_reductions<real>(b);
 }
+
+
 
 // Store pre-collision populations (or the equilibrium at rest of a density field)
 // as the current state; its mass partials go where the next collide kernel reads them.
@@ -196,4 +216,5 @@ int init_fields(lbm_ctx* h, const double* rho0, const double* T0, const double* 
   template void gather_populations<T>(lbm_ctx*, T*);                                        \
   template int init_fields<T>(lbm_ctx*, const double*, const double*, const double*);       \
   template void batch_step_once<T>(lbm_batch*);                                             \
+  template void batch_finish_reductions<T>(lbm_batch*);                                             \
   }
