@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WP
     k_energy_rows_batch(const DomainDev* __restrict__ tab, int ndom, int fpost, int tcur, int cur,
                         int hslot, int sub, double dtd) {
   if (batch_outlet<float, NW>(tab, ndom, fpost, cur, sub)) return;
-  const int g = xcd_tile(blockIdx.x - ndom, gridDim.x - ndom);
+  const int g = xcd_tile_edges_first(blockIdx.x - ndom, gridDim.x - ndom);
   const int d = batch_domain<true>(tab, ndom, g);
   const DomainDev& D = tab[d];
   const Layout& L = D.L;
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(NW * 64)
     k_energy_batch(const DomainDev* __restrict__ tab, int ndom, int fpost, int tcur, int cur, int hslot,
                    int sub, double dtd) {
   if (batch_outlet<real, NW>(tab, ndom, fpost, cur, sub)) return;
-  const int g = xcd_tile(blockIdx.x - ndom, gridDim.x - ndom);
+  const int g = xcd_tile_edges_first(blockIdx.x - ndom, gridDim.x - ndom);
   const int d = batch_domain<true>(tab, ndom, g);
   const DomainDev& D = tab[d];
   const Layout& L = D.L;

@@ -401,7 +401,7 @@ __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WP
     return;
   }
   energy_rows_step<NW, B>(P, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
-                          xcd_tile(blockIdx.x - 1, P.nblkE));
+                          xcd_tile_edges_first(blockIdx.x - 1, P.nblkE));
 }
 
 }  // namespace lbmk

@@ -73,6 +73,16 @@ __device__ __forceinline__ void energy_tile_rows(const KParams& P, int tile, int
   ty = min(tr == 0 ? P.tyE0 : P.tyE, P.nT - j0);
 }
 
+// The energy grids' order: as xcd_tile, but every odd band is dispatched from its last
+// tile down.  The top tile row (end of the last band) and the bottom one (start of the
+// first band) then start first on their XCDs.  They run the slower boundary code, and
+// the oldest waves on a CU get issue priority.
+__device__ __forceinline__ int xcd_tile_edges_first(int b, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7, k = b & 7, pos = b >> 3;
+  const int start = k * q + (k < r ? k : r), cnt = q + (k < r ? 1 : 0);
+  return start + ((k & 1) ? cnt - 1 - pos : pos);
+}
+
 // 1/v: exact for FP64, the hardware reciprocal (1 ulp) for FP32
 template <typename real>
 __device__ __forceinline__ real fast_rcp(real v) {
@@ -1106,7 +1116,7 @@ __global__ void __launch_bounds__(NW * 64)
     return;
   }
   energy_lds_tile<real, ISO, NW, HMAX>(P, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
-                                       xcd_tile(blockIdx.x - 1, P.nblkE));
+                                       xcd_tile_edges_first(blockIdx.x - 1, P.nblkE));
 }
 
 // ---------------------------------------------------------------------------
