@@ -207,7 +207,9 @@ int lbm_destroy(lbm_ctx *h);
  * device as one large domain would.  Each domain evolves exactly as it would alone with
  * the same tile_rows.  The workspace holds a device table of the domains followed by
  * each domain's own workspace; ownership, streams and errors are as for one domain.
- * lbm_batch_step has the same graph-capture property as lbm_step.
+ * lbm_batch_step has the same graph-capture property as lbm_step.  The per-step
+ * diagnostics of all domains are folded together (two launches for the whole batch) at
+ * the end of every 256th step and in lbm_batch_observe.
  */
 typedef struct lbm_batch lbm_batch;
 
