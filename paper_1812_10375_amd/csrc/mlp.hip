@@ -49,6 +49,9 @@ struct Gemm {
   const float* Zin;  // pre-activation for the GELU derivative [m * ldz + n + z * szz]
   long ldz, szz;
   int nvalid;  // columns written by EPI_BIAS_OUT
+  const float* Dsum;  // split-K only: blocks of the first tile row also sum the columns of
+  float* dbias;       // Dsum ([K][N] per member, stride sdsum) into dbias (stride sdbias)
+  long sdsum, sdbias;
 };
 
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
@@ -107,6 +110,27 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const Gemm g) {
   }
 }
 
+// db[n] = sum over rows of D[row][n] for the 16 columns n0 .. n0 + 15 (n < N, row < B),
+// in a fixed order, by a block of 1024 threads: thread (g, c) sums rows g, g + 64, ...
+// of column n0 + c in order, and the 64 row-group partials are added pairwise in LDS.
+// Every thread of the block must call it.
+constexpr int CS_THREADS = 1024, CS_COLS = 16, CS_GROUPS = CS_THREADS / CS_COLS;
+__device__ __forceinline__ void colsum16(const float* __restrict__ D, int B, int N, int n0, float* __restrict__ db) {
+  __shared__ float part[CS_GROUPS][CS_COLS];
+  const int c = threadIdx.x % CS_COLS, grp = threadIdx.x / CS_COLS;
+  const int n = n0 + c;
+  float s = 0.f;
+  if (n < N)
+    for (int b = grp; b < B; b += CS_GROUPS) s += D[(long)b * N + n];
+  part[grp][c] = s;
+  __syncthreads();
+  for (int h = CS_GROUPS / 2; h > 0; h >>= 1) {
+    if (grp < h) part[grp][c] += part[grp + h][c];
+    __syncthreads();
+  }
+  if (grp == 0 && n < N) db[n] = part[0][c];
+}
+
 // The weight-gradient products contract over the batch (K = B rows) into few output
 // tiles.  Here the 16 waves of a block share one 16 x 16 tile: wave w takes the k-steps
 // w, w + 16, ... of 32, and lane l of wave 0 adds the 16 partial tiles in wave order.
@@ -134,6 +158,7 @@ __global__ void __launch_bounds__(SK_WAVES * 64) k_gemm_bf16_splitk(const Gemm g
     }
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
   }
+  if (g.dbias && m0 == 0) colsum16(g.Dsum + z * g.sdsum, g.K, g.N, n0, g.dbias + z * g.sdbias);
   part[wave][lane] = acc;
   __syncthreads();
   if (wave != 0) return;
@@ -159,12 +184,14 @@ __global__ void k_prep_x(const float* __restrict__ x, long sx, __bf16* __restric
   }
 }
 
+
 // dY = 2 (Y - T) / B on the 2 outputs (zero on the padded columns), and the loss of
 // each member: one block per member, fixed-order reduction.
 constexpr int OG_THREADS = 1024;
 __global__ void __launch_bounds__(OG_THREADS) k_out_grad(const float* __restrict__ Y, const float* __restrict__ T, long st,
                                                    int B, float* __restrict__ dYf, __bf16* __restrict__ dYb,
-                                                   float* __restrict__ loss, long sy, long sd) {
+                                                   float* __restrict__ loss, long sy, long sd,
+                                                   float* __restrict__ db3, long sdb) {
   __shared__ float red[OG_THREADS];
   const int z = blockIdx.x;
   const float inv = 1.f / (float)B;
@@ -188,27 +215,8 @@ __global__ void __launch_bounds__(OG_THREADS) k_out_grad(const float* __restrict
     __syncthreads();
   }
   if (threadIdx.x == 0) loss[z] = red[0] * inv;
-}
-
-// db[n] = sum over rows of D[row][n] (n < N, row < B), per member, in a fixed order: a
-// block of 1024 threads covers 16 columns; thread (g, c) sums rows g, g + 64, ... of
-// column c in order, and the 64 row-group partials are then added pairwise in LDS.
-constexpr int CS_THREADS = 1024, CS_COLS = 16, CS_GROUPS = CS_THREADS / CS_COLS;
-__global__ void __launch_bounds__(CS_THREADS) k_colsum(const float* __restrict__ D, int B, int N, long sdz,
-                                                       float* __restrict__ db, long sbz) {
-  __shared__ float part[CS_GROUPS][CS_COLS];
-  const int z = blockIdx.y, c = threadIdx.x % CS_COLS, grp = threadIdx.x / CS_COLS;
-  const int n = blockIdx.x * CS_COLS + c;
-  float s = 0.f;
-  if (n < N)
-    for (int b = grp; b < B; b += CS_GROUPS) s += D[z * sdz + (long)b * N + n];
-  part[grp][c] = s;
-  __syncthreads();
-  for (int h = CS_GROUPS / 2; h > 0; h >>= 1) {
-    if (grp < h) part[grp][c] += part[grp + h][c];
-    __syncthreads();
-  }
-  if (grp == 0 && n < N) db[z * sbz + n] = part[0][c];
+  // bias gradient of the output layer: the column sums of dY
+  colsum16(dYf + z * sd, B, NP3, 0, db3 + z * sdb);
 }
 
 __global__ void k_to_bf16(const float* __restrict__ w, __bf16* __restrict__ wb, long n) {
@@ -288,7 +296,9 @@ int hip_rc(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 template <int EPI>
 void gemm(lbm_mlp* m, const Gemm& g) {
   const int tiles = ((g.M + 15) / 16) * ((g.N + 15) / 16);
-  if (EPI == EPI_F32 && g.K >= 32 * SK_WAVES)  // long contraction into few tiles: split it
+  // long contractions into few tiles are split over K; so are those that also sum
+  // bias-gradient columns, which the split kernel does in its first tile row
+  if (EPI == EPI_F32 && (g.K >= 32 * SK_WAVES || g.dbias))
     hipLaunchKernelGGL(k_gemm_bf16_splitk, dim3(tiles, m->members), dim3(SK_WAVES * 64), 0, m->stream, g);
   else
     hipLaunchKernelGGL(k_gemm_bf16<EPI>, dim3((tiles + 3) / 4, m->members), dim3(256), 0, m->stream, g);
@@ -457,9 +467,9 @@ int lbm_mlp_backward(lbm_mlp* m, const float* d_x, const float* d_t, int B, int 
   float* Y = m->at<float>(L.y);
   const long sx = per_member ? (long)B * IN : 0, st = per_member ? (long)B * OUT : 0;
   forward(m, d_x, sx, B, Y, A * OUT);
-  hipLaunchKernelGGL(k_out_grad, dim3(m->members), dim3(OG_THREADS), 0, m->stream, Y, d_t, st, B, m->at<float>(L.dyf),
-                     m->at<__bf16>(L.dyb), d_loss, A * OUT, A * NP3);
   float* gr = m->at<float>(L.g);
+  hipLaunchKernelGGL(k_out_grad, dim3(m->members), dim3(OG_THREADS), 0, m->stream, Y, d_t, st, B, m->at<float>(L.dyf),
+                     m->at<__bf16>(L.dyb), d_loss, A * OUT, A * NP3, gr + OFF_B3, (long)PP);
   const __bf16* wb = m->at<__bf16>(L.wb);
   Gemm g = blank();
   // dW3 = H2^T dY (128 x 16)
@@ -468,8 +478,6 @@ int lbm_mlp_backward(lbm_mlp* m, const float* d_x, const float* d_t, int B, int 
   g.M = H; g.N = NP3; g.K = B;
   g.Cf = gr + OFF_W3; g.ldc = NP3; g.scf = PP;
   gemm<EPI_F32>(m, g);
-  hipLaunchKernelGGL(k_colsum, dim3((NP3 + CS_COLS - 1) / CS_COLS, m->members), dim3(CS_THREADS), 0, m->stream, m->at<float>(L.dyf), B, NP3,
-                     A * NP3, gr + OFF_B3, (long)PP);
   // dZ2 = (dY W3^T) * gelu'(Z2)
   g = blank();
   g.A = m->at<__bf16>(L.dyb); g.sam = NP3; g.sak = 1; g.saz = A * NP3;
@@ -485,9 +493,8 @@ int lbm_mlp_backward(lbm_mlp* m, const float* d_x, const float* d_t, int B, int 
   g.B = m->at<__bf16>(L.d2b); g.sbk = H; g.sbn = 1; g.sbz = A * H;
   g.M = H; g.N = H; g.K = B;
   g.Cf = gr + OFF_W2; g.ldc = H; g.scf = PP;
+  g.Dsum = m->at<float>(L.d2f); g.sdsum = A * H; g.dbias = gr + OFF_B2; g.sdbias = PP;  // db2 = column sums of dZ2
   gemm<EPI_F32>(m, g);
-  hipLaunchKernelGGL(k_colsum, dim3((H + CS_COLS - 1) / CS_COLS, m->members), dim3(CS_THREADS), 0, m->stream, m->at<float>(L.d2f), B, H, A * H,
-                     gr + OFF_B2, (long)PP);
   // dZ1 = (dZ2 W2^T) * gelu'(Z1)
   g = blank();
   g.A = m->at<__bf16>(L.d2b); g.sam = H; g.sak = 1; g.saz = A * H;
@@ -503,9 +510,8 @@ int lbm_mlp_backward(lbm_mlp* m, const float* d_x, const float* d_t, int B, int 
   g.B = m->at<__bf16>(L.d1b); g.sbk = H; g.sbn = 1; g.sbz = A * H;
   g.M = KP1; g.N = H; g.K = B;
   g.Cf = gr + OFF_W1; g.ldc = H; g.scf = PP;
+  g.Dsum = m->at<float>(L.d1f); g.sdsum = A * H; g.dbias = gr + OFF_B1; g.sdbias = PP;  // db1 = column sums of dZ1
   gemm<EPI_F32>(m, g);
-  hipLaunchKernelGGL(k_colsum, dim3((H + CS_COLS - 1) / CS_COLS, m->members), dim3(CS_THREADS), 0, m->stream, m->at<float>(L.d1f), B, H, A * H,
-                     gr + OFF_B1, (long)PP);
   return hip_rc(hipGetLastError());
 }
 
