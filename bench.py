@@ -38,22 +38,58 @@ def algorithmic_flops(sc):
     return (4 * 42 + 46) * fluid + (4 * 16 + 10) * heater
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of later parallel regions started from this thread
+    (the oracle's loops); returns the previous maximum."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    prev = gomp.omp_get_max_threads()
+    gomp.omp_set_num_threads(int(n))
+    return prev
+
+
 def cpu_baseline(sc, budget_s=20.0):
-    """FP64 oracle on the same workload, for as many steps as fit in about budget_s."""
+    """FP64 oracle on the same workload: as many steps as fit in about two thirds of
+    budget_s on all the host threads OpenMP is given, then about a third of it on one
+    thread (the oracle as it stands, untuned)."""
     from oracle.lbm import OracleSim
-    orc = OracleSim(sc)
-    t0 = time.perf_counter()
-    orc.step(1)
-    t1 = time.perf_counter() - t0
-    n = max(1, min(1000, int(budget_s / max(t1, 1e-6)) - 1))
-    t0 = time.perf_counter()
-    orc.step(n)
-    dt = time.perf_counter() - t0
     nodes = sc["nx"] * sc["ny"]
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": "%d steps (after 1 untimed) of the same %dx%d+%d workload, FP64, %.1f s"
-                      % (n, sc["nx"], sc["ny"], sc["heater_rows"], dt)}
+    orc = OracleSim(sc)
+
+    def rate(seconds):
+        t0 = time.perf_counter()
+        orc.step(1)
+        t1 = time.perf_counter() - t0
+        n = max(1, min(1000, int(seconds / max(t1, 1e-6)) - 1))
+        t0 = time.perf_counter()
+        orc.step(n)
+        dt = time.perf_counter() - t0
+        return nodes * n / dt / 1e6, n, dt
+
+    import ctypes
+    cores = ctypes.CDLL("libgomp.so.1").omp_get_max_threads()
+    v_all, n_all, dt_all = rate(budget_s * 2.0 / 3.0)
+    prev = _omp_threads(1)
+    try:
+        v_one, n_one, dt_one = rate(budget_s / 3.0)
+    finally:
+        _omp_threads(prev)
+    return {"value": v_all, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "value_1thread": v_one, "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": "%d steps on %d threads (%.1f s) and %d steps on 1 thread (%.1f s), each after "
+                      "1 untimed step, of the same %dx%d+%d workload, FP64"
+                      % (n_all, cores, dt_all, n_one, dt_one, sc["nx"], sc["ny"], sc["heater_rows"])}
 
 
 KERNEL_SOURCES = ("lbm_kernels.hpp", "lbm_energy_f32.hpp")
@@ -146,7 +182,7 @@ def hbm_resident(n=4096, steps=100, warmup=10):
     import torch
     from paper_1812_10375_amd import scenarios as S
     from paper_1812_10375_amd.lbm import Lattice
-    sc = S.pool_boiling(nx=n, ny=n)
+    sc = S.pool_boiling(nx=n, ny=n, liquid_fraction=1.0)
     lat = Lattice(sc)
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -220,10 +256,8 @@ def boiling_curve(n_query=10000, cases=((512, 0.05), (2048, 0.0075))):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # the workload's vapour layer is blown out through the outlet after ~1300 steps
-    # (see the design notes), so warm-up plus both timed regions stay below that
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--ny", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -257,7 +291,11 @@ def main():
     from paper_1812_10375_amd import scenarios as S
     from paper_1812_10375_amd.lbm import Lattice
 
-    sc = S.pool_boiling(nx=args.nx, ny=args.ny)
+    # the pool starts filled with liquid, as the paper's boiling runs do (Sec. 4.2); a
+    # pool filled to 70% loses its vapour layer through the outlet after about 1300
+    # steps under Eq. 9's domain-mean rho_ave, and the step's work does not depend on
+    # the state
+    sc = S.pool_boiling(nx=args.nx, ny=args.ny, liquid_fraction=1.0)
     lat = Lattice(sc)
     stream = lat.stream
     lat.step(args.warmup)
@@ -281,6 +319,16 @@ def main():
     ms_events = start.elapsed_time(stop)
     kt = lat.kernel_times()
     lat.set_kernel_timing(False)
+    # sustained rate: median over 5 further regions of max(steps, 2000) steps
+    sus = []
+    for _ in range(5):
+        k = max(args.steps, 2000)
+        start.record(stream)
+        lat.step(k)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        sus.append(start.elapsed_time(stop) / k)
+    sus.sort()
     ob = lat.observe(check=False)
     nodes = sc["nx"] * sc["ny"]
     mlups = nodes * args.steps / (ms * 1e-3) / 1e6
@@ -302,6 +350,7 @@ def main():
                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_TFLOPS, "traffic": recorded_traffic("k_energy_rows"),
                     "kernel": "k_energy_rows", "per_launch": af, "avg_launch_ms": per[dom]}
     step_bytes = algorithmic_bytes(sc) + 8 * sc["nx"] * (sc["ny"] + sc["heater_rows"])
+    step_gbps = step_bytes / (ms / args.steps * 1e-3) / 1e9
     out = {
         "metric": "MLUPS 1024\u00b2 FP32 plain; boiling-curve pts/hr batched+surrogate vs plain",
         "value": mlups,
@@ -317,11 +366,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc["name"] + "+%d_heater" % sc["heater_rows"], "nx": sc["nx"],
                    "ny": sc["ny"], "heater_rows": sc["heater_rows"], "sites": int(len(sc["sites"])),
-                   "superheat_Tc": 0.10, "g": sc["g"], "seed": sc["seed"]},
+                   "superheat_Tc": 0.10, "g": sc["g"], "seed": sc["seed"],
+                   "initial_state": "all liquid (Sec. 4.2)"},
         "roofline": roofline,
         "kernels_ms": {k: per[k] for k in per},
         "ms_per_step_with_kernel_events": ms_events / args.steps,
-        "step_algorithmic_GBps": step_bytes / (ms / args.steps * 1e-3) / 1e9,
+        "step_algorithmic_GBps": step_gbps,
+        # the whole step against HBM: 80 B per fluid node (populations and temperature
+        # read and written once) plus 8 B per heater node, over the measured step time;
+        # the target is 0.6
+        "step_roofline": {"bound": "hbm", "bytes_per_step": step_bytes, "achieved": step_gbps,
+                          "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": step_gbps / HBM_PEAK_GBPS,
+                          "target_frac": 0.6},
+        "sustained": {"regions": 5, "steps_each": max(args.steps, 2000), "ms_per_step_median": sus[2],
+                      "MLUPS_median": nodes / (sus[2] * 1e-3) / 1e6,
+                      "step_frac_median": step_bytes / (sus[2] * 1e-3) / 1e9 / HBM_PEAK_GBPS},
         "status": ob["status"],
     }
     lat.close()

@@ -158,11 +158,12 @@ def pool_boiling(nx=1024, ny=1024, heater_rows=25, superheat=0.10, g=3e-5, n_sit
 BATCH_SIZES = ((256, 256), (512, 256), (512, 512), (1024, 512))  # (nx, ny)
 
 
-def batched_pool_boiling(n=48, seed=7, heater_rows=25, precision="f32", steps=50000):
+def batched_pool_boiling(n=48, seed=7, heater_rows=25, precision="f32", steps=50000, liquid_fraction=1.0):
     """Independent pool-boiling domains of uneven sizes for the batched step: sizes drawn
     from BATCH_SIZES, superheats from U(0.02, 0.30) Tc, 2-12 nucleation sites per domain
     (periodic minimum spacing nx / (2 n_sites), at least 8 columns), every domain seeded
-    from one generator."""
+    from one generator.  The pools start filled with liquid, as the paper's boiling runs
+    do (Sec. 4.2)."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
@@ -171,7 +172,8 @@ def batched_pool_boiling(n=48, seed=7, heater_rows=25, precision="f32", steps=50
         n_sites = int(rng.integers(2, 13))
         sc = pool_boiling(nx=nx, ny=ny, heater_rows=heater_rows, superheat=superheat,
                           n_sites=n_sites, min_spacing=max(8, nx // (2 * n_sites)),
-                          seed=int(rng.integers(0, 2**31)), precision=precision, steps=steps)
+                          seed=int(rng.integers(0, 2**31)), precision=precision, steps=steps,
+                          liquid_fraction=liquid_fraction)
         sc["name"] = "batch%02d_%s" % (i, sc["name"])
         out.append(sc)
     return out
