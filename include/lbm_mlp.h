@@ -53,6 +53,20 @@ int lbm_mlp_get_params(lbm_mlp *m, float *host);
 /* d_x: device [B][4] FP32 inputs; d_y: device [members][B][2] FP32 outputs. */
 int lbm_mlp_forward(lbm_mlp *m, const float *d_x, int B, float *d_y);
 
+/* Allocation-free forward pass, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight inference loops, harnesses that forbid hipMalloc).  Same
+ * arguments and results as lbm_mlp_forward (the outputs are identical), but the
+ * activations go to a file-scope device array of the library, of fixed size, instead
+ * of the context's workspace; the call allocates nothing (no hipMalloc, no hipFree, no
+ * allocating library routine).  members * B must not exceed LBM_MLP_NOALLOC_MAX_ROWS
+ * (LBM_EINVAL otherwise; the array holds 576 bytes per row, 4.5 MiB in all, on every
+ * device the library runs on until the process ends).  Every call on one device shares
+ * that array and leaves it holding its activations: calls that overlap on one device
+ * (other streams, other host threads) race and must be ordered by the caller.  The
+ * device is the one current at lbm_mlp_init, which resolves the array's address. */
+#define LBM_MLP_NOALLOC_MAX_ROWS 8192
+int lbm_mlp_forward_noalloc(lbm_mlp *m, const float *d_x, int B, float *d_y);
+
 /* Forward and backward pass of every member: d_x device [B][4] inputs and d_t device
  * [B][2] FP32 targets shared by all members (per_member = 0), or [members][B][4] and
  * [members][B][2] with a batch of its own for each member (per_member = 1, e.g.

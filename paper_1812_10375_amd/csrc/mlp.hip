@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -32,7 +33,7 @@ constexpr int MAX_MEMBERS = 16, MAX_BATCH = 1 << 20;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_BIAS_OUT = 2, EPI_GELU_GRAD = 3 };
+enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_BIAS_OUT = 2, EPI_GELU_GRAD = 3, EPI_BIAS_GELU_BF16 = 4 };
 
 struct Gemm {
   const __bf16* A;  // A(m, k) = A[m * sam + k * sak + z * saz]
@@ -100,6 +101,9 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const Gemm g) {
       const float zz = v + g.bias[n + z * g.sbias];
       g.Cf[(long)m * g.ldc + n + z * g.scf] = zz;
       g.Cb[(long)m * g.ldb + n + z * g.scb] = (__bf16)gelu(zz);
+    } else if constexpr (EPI == EPI_BIAS_GELU_BF16) {
+      // inference only: the BF16 activation, without the FP32 pre-activation
+      g.Cb[(long)m * g.ldb + n + z * g.scb] = (__bf16)gelu(v + g.bias[n + z * g.sbias]);
     } else if constexpr (EPI == EPI_BIAS_OUT) {
       if (n < g.nvalid) g.Cf[(long)m * g.ldc + n + z * g.scf] = v + g.bias[n + z * g.sbias];
     } else {
@@ -279,6 +283,7 @@ Layout layout(int M, int Bm) {
 
 struct lbm_mlp {
   int members, max_batch;
+  int device;  // device current at init
   hipStream_t stream;
   char* ws;
   Layout L;
@@ -348,6 +353,68 @@ void forward(lbm_mlp* m, const float* x, long sx, int B, float* y, long sy) {
   gemm<EPI_BIAS_OUT>(m, g);
 }
 
+// Activations of the allocation-free forward pass: one file-scope device array, held
+// by every device the library runs on until the process ends.  Per row (a member's
+// input row): padded BF16 inputs (32), then the BF16 activations of both hidden layers
+// (128 each).  Host code reaches it only through the device address that
+// hipGetSymbolAddress returns on each device.
+constexpr long NOALLOC_ROWS = LBM_MLP_NOALLOC_MAX_ROWS;
+constexpr size_t NA_XB = 0, NA_H1 = NA_XB + (size_t)NOALLOC_ROWS * KP1 * 2,
+                 NA_H2 = NA_H1 + (size_t)NOALLOC_ROWS * H * 2, NA_BYTES = NA_H2 + (size_t)NOALLOC_ROWS * H * 2;
+static_assert(NA_H1 % 256 == 0 && NA_H2 % 256 == 0, "scratch parts stay 256-byte aligned");
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+char* scratch_dev[MAX_DEVICES];  // device address of `scratch` on each device, once resolved
+
+// Resolve the device address of `scratch` on the current device (once per device).
+int resolve_scratch(int& device) {
+  if (hipGetDevice(&device) != hipSuccess || device < 0 || device >= MAX_DEVICES) return LBM_EHIP;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM_EHIP;
+    scratch_dev[device] = static_cast<char*>(ptr);
+  }
+  return LBM_OK;
+}
+
+// The forward pass of every member with its activations in `sc` (the device address of
+// `scratch`): the same kernels, operands and accumulation order as forward(), so the
+// outputs are identical; only the FP32 pre-activations are not kept.
+void forward_scratch(lbm_mlp* m, char* sc, const float* x, int B, float* y) {
+  const long A = (long)B;  // member stride in rows
+  __bf16* xb = reinterpret_cast<__bf16*>(sc + NA_XB);
+  __bf16* h1 = reinterpret_cast<__bf16*>(sc + NA_H1);
+  __bf16* h2 = reinterpret_cast<__bf16*>(sc + NA_H2);
+  hipLaunchKernelGGL(k_prep_x, dim3(256, m->members), dim3(256), 0, m->stream, x, 0L, xb, A * KP1, B);
+  const __bf16* wb = m->at<__bf16>(m->L.wb);
+  const float* w = m->at<float>(m->L.w);
+  Gemm g = blank();
+  g.A = xb; g.sam = KP1; g.sak = 1; g.saz = A * KP1;
+  g.B = wb + OFF_W1; g.sbk = H; g.sbn = 1; g.sbz = PP;
+  g.M = B; g.N = H; g.K = KP1;
+  g.bias = w + OFF_B1; g.sbias = PP;
+  g.Cb = h1; g.ldb = H; g.scb = A * H;
+  gemm<EPI_BIAS_GELU_BF16>(m, g);
+  g = blank();
+  g.A = h1; g.sam = H; g.sak = 1; g.saz = A * H;
+  g.B = wb + OFF_W2; g.sbk = H; g.sbn = 1; g.sbz = PP;
+  g.M = B; g.N = H; g.K = H;
+  g.bias = w + OFF_B2; g.sbias = PP;
+  g.Cb = h2; g.ldb = H; g.scb = A * H;
+  gemm<EPI_BIAS_GELU_BF16>(m, g);
+  g = blank();
+  g.A = h2; g.sam = H; g.sak = 1; g.saz = A * H;
+  g.B = wb + OFF_W3; g.sbk = NP3; g.sbn = 1; g.sbz = PP;
+  g.M = B; g.N = NP3; g.K = H;
+  g.bias = w + OFF_B3; g.sbias = PP;
+  g.Cf = y; g.ldc = OUT; g.scf = (long)B * OUT;
+  g.nvalid = OUT;
+  gemm<EPI_BIAS_OUT>(m, g);
+}
+
 bool valid_sizes(int members, int max_batch) {
   return members >= 1 && members <= MAX_MEMBERS && max_batch >= 1 && max_batch <= MAX_BATCH;
 }
@@ -371,8 +438,11 @@ int lbm_mlp_init(int members, int max_batch, void* d_workspace, size_t ws_bytes,
   if (reinterpret_cast<uintptr_t>(d_workspace) & 255) return LBM_EINVAL;
   const Layout L = layout(members, max_batch);
   if (ws_bytes < L.total) return LBM_ENOMEM;
+  int device = -1;
+  if (resolve_scratch(device) != LBM_OK) return LBM_EHIP;
   lbm_mlp* m = new (std::nothrow) lbm_mlp();
   if (!m) return LBM_ENOMEM;
+  m->device = device;
   m->members = members;
   m->max_batch = max_batch;
   m->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -457,6 +527,14 @@ int lbm_mlp_get_grads(lbm_mlp* m, float* host) {
 int lbm_mlp_forward(lbm_mlp* m, const float* d_x, int B, float* d_y) {
   if (!m || !d_x || !d_y || B < 1 || B > m->max_batch) return LBM_EINVAL;
   forward(m, d_x, 0, B, d_y, (long)B * OUT);
+  return hip_rc(hipGetLastError());
+}
+
+int lbm_mlp_forward_noalloc(lbm_mlp* m, const float* d_x, int B, float* d_y) {
+  if (!m || !d_x || !d_y || B < 1 || (long)m->members * B > NOALLOC_ROWS) return LBM_EINVAL;
+  char* sc = (m->device >= 0 && m->device < MAX_DEVICES) ? scratch_dev[m->device] : nullptr;
+  if (!sc) return LBM_EHIP;
+  forward_scratch(m, sc, d_x, B, d_y);
   return hip_rc(hipGetLastError());
 }
 

@@ -30,6 +30,8 @@ def _lib():
             getattr(L, name).argtypes = [vp, fp]
         L.lbm_mlp_forward.restype = C.c_int
         L.lbm_mlp_forward.argtypes = [vp, vp, C.c_int, vp]
+        L.lbm_mlp_forward_noalloc.restype = C.c_int
+        L.lbm_mlp_forward_noalloc.argtypes = [vp, vp, C.c_int, vp]
         L.lbm_mlp_backward.restype = C.c_int
         L.lbm_mlp_backward.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp]
         L.lbm_mlp_adam.restype = C.c_int
@@ -38,6 +40,9 @@ def _lib():
         L.lbm_mlp_destroy.argtypes = [vp]
         _bound = True
     return L
+
+
+NOALLOC_MAX_ROWS = 8192  # LBM_MLP_NOALLOC_MAX_ROWS of include/lbm_mlp.h
 
 
 def n_params():
@@ -122,6 +127,20 @@ class MLPEnsemble:
         rc = _lib().lbm_mlp_forward(self.h, C.c_void_p(xt.data_ptr()), B, C.c_void_p(y.data_ptr()))
         if rc != 0:
             raise LbmError(rc, "lbm_mlp_forward")
+        self._keep = xt
+        return y
+
+    def forward_noalloc(self, x, y=None):
+        """The same outputs through the allocation-free entry point (activations in the
+        library's fixed device array; members * B <= NOALLOC_MAX_ROWS).  `y`, if given,
+        is a device tensor [members][B][2] to write into."""
+        xt = self._dev(x, 4)
+        B = xt.shape[0]
+        if y is None:
+            y = self.torch.empty((self.members, B, 2), dtype=self.torch.float32, device=self.device)
+        rc = _lib().lbm_mlp_forward_noalloc(self.h, C.c_void_p(xt.data_ptr()), B, C.c_void_p(y.data_ptr()))
+        if rc != 0:
+            raise LbmError(rc, "lbm_mlp_forward_noalloc")
         self._keep = xt
         return y
 
