@@ -60,7 +60,14 @@ enum {
   LBM_FREEZE_EOS_T = 1u,   /* EOS of Eq. 7 evaluated at T_sat (Sec. 3.2)          */
   LBM_NO_ADVECTION = 2u,   /* drop -u.grad T from Eq. 17                          */
   LBM_NO_LATENT = 4u,      /* drop the (dp/dT)_v div(u) term from Eq. 17          */
-  LBM_DIFF_ISOTROPIC = 8u  /* diffusion by Eq. 20-21 (comparison scheme)          */
+  LBM_DIFF_ISOTROPIC = 8u, /* diffusion by Eq. 20-21 (comparison scheme)          */
+  LBM_TWO_LAUNCHES = 32u,  /* FP32 with n_sub = 1: run each step as a collide launch
+                              followed by an energy launch ...                       */
+  LBM_ONE_LAUNCH = 64u     /* ... or as one fused launch.  Without either flag the
+                              library picks by grid size (fused when the collide tiles
+                              fill the device's workgroup slots in one round).  A
+                              performance knob: the results are identical.  Setting
+                              both is an error.                                      */
 };
 
 /*
@@ -136,7 +143,10 @@ typedef struct {
   int64_t first_bad_step;
 } lbm_obs;
 
-enum { LBM_ERR_RHO = 1, LBM_ERR_COVOLUME = 2, LBM_ERR_RADICAND = 4, LBM_ERR_NONFINITE = 8 };
+/* LBM_ERR_SYNC: in the fused FP32 step a workgroup waited too long (about a second) for
+ * the collide tiles it depends on, for example because other work occupied the device
+ * and delayed their dispatch; the step's results are not trustworthy. */
+enum { LBM_ERR_RHO = 1, LBM_ERR_COVOLUME = 2, LBM_ERR_RADICAND = 4, LBM_ERR_NONFINITE = 8, LBM_ERR_SYNC = 16 };
 
 /* Fields for lbm_read_field / lbm_write_field; element type is the context's precision.
  *   LBM_FIELD_F    9 x ny x nx pre-collision populations f^n (x fastest)   read/write

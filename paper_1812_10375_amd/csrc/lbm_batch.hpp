@@ -23,8 +23,8 @@ __device__ __forceinline__ int batch_domain(const DomainDev* __restrict__ tab, i
   return lo;
 }
 
-template <typename real, int TY>
-__global__ void __launch_bounds__(NT)
+template <typename real, int TY, int NW>
+__global__ void __launch_bounds__(NW * 64)
     k_collide_batch(const DomainDev* __restrict__ tab, int ndom, int fcur, int tcur, int cur) {
   const int g = xcd_tile(blockIdx.x, gridDim.x);
   const int d = batch_domain<false>(tab, ndom, g);
@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(NT)
   const Layout& L = D.L;
   char* ws = D.ws;
   const int prev = 1 - cur;
-  collide_tile<real, TY>(
+  collide_tile<real, TY, NW, false>(
       D.P, reinterpret_cast<const real*>(ws + L.f[fcur]), reinterpret_cast<real*>(ws + L.f[1 - fcur]),
       reinterpret_cast<const real*>(ws + L.topin), reinterpret_cast<const real*>(ws + L.T[tcur]),
       reinterpret_cast<const real*>(ws + L.gw), reinterpret_cast<real*>(ws + L.rho),

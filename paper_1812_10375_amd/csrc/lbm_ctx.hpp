@@ -12,10 +12,11 @@
 
 namespace lbmh {
 
-// Tiles.  k_collide: 64 columns x TY rows, 256 threads.  k_energy: txE <= E_TXMAX
-// columns x tyE rows (E_HMIN <= tyE <= E_HMAX), E_NW waves; the sizes are chosen per
-// grid so that the tiles fill the CUs in one round when the grid allows it.
-constexpr int TY_F32 = 16, TY_F64 = 8;
+// Tiles.  k_collide: 64 columns x TY rows, NWC waves (the fused FP32 step runs two
+// collide tiles per workgroup, the size of an energy workgroup).  k_energy: txE <=
+// E_TXMAX columns x tyE rows (E_HMIN <= tyE <= E_HMAX), E_NW waves; the sizes are chosen
+// per grid so that the tiles fill the CUs in one round when the grid allows it.
+constexpr int TY_F32 = 16, TY_F64 = 8, NWC = 4;
 constexpr int E_NW = 8, E_HMAX = 48, E_HMIN = 8, E_TXMAX = 56;
 // FP32 register-row energy kernel: E_RNW waves of E_BAND rows each, E_RWPE waves per
 // SIMD (two workgroups per CU)
@@ -44,6 +45,7 @@ struct lbm_ctx {
   bool bad;
   int hist_first, hist_count;  // history slots of the steps not yet folded in
   int ncu;                     // compute units of the device
+  bool fused;                  // FP32 steps run as one fused launch (k_step_fused)
   long long step_staging;      // host copy source for the device step counter
   // optional per-kernel timing: events recorded in pairs (start, stop) per launch
   bool timing;

@@ -45,8 +45,9 @@ struct RowsShared {
 
 // The tile work.  PLAIN: every row of the tile (halo included) is a fluid row away from
 // both boundaries, so no row needs boundary handling and none is skipped, and advection
-// and the latent term are both on.
-template <int NW, int B, bool PLAIN>
+// and the latent term are both on.  COH: rho and u come from collide tiles of the same
+// launch (the fused step) and are loaded coherently.
+template <int NW, int B, bool PLAIN, bool COH>
 __device__ __forceinline__ void energy_rows_tile(
     const KParams& P, RowsShared<NW, B>& sh, const float* __restrict__ Tin, float* __restrict__ Tout,
     const float* __restrict__ rho, const float* __restrict__ uxa, const float* __restrict__ uya,
@@ -78,9 +79,15 @@ __device__ __forceinline__ void energy_rows_tile(
         const int j = min(max(jb - 1 + q, nh), nT - 1);
         lT[q] = ld32(Tin, (unsigned)j * (unsigned)nx + gx);
         const unsigned n = (unsigned)(j - nh) * (unsigned)nx + gx;
-        lR[q] = ld32(rho, n);
-        lU[q] = ld32(uxa, n);
-        lV[q] = ld32(uya, n);
+        if constexpr (COH) {
+          lR[q] = ldc<true>(rho + n);
+          lU[q] = ldc<true>(uxa + n);
+          lV[q] = ldc<true>(uya + n);
+        } else {
+          lR[q] = ld32(rho, n);
+          lU[q] = ld32(uxa, n);
+          lV[q] = ld32(uya, n);
+        }
       }
     } else {
 #pragma unroll
@@ -100,14 +107,14 @@ __device__ __forceinline__ void energy_rows_tile(
         lT[q] = Tin[(size_t)j * nx + gx];
         if (j >= nh) {
           const size_t n = (size_t)(j - nh) * nx + gx;
-          lR[q] = rho[n];
-          lU[q] = uxa[n];
-          lV[q] = uya[n];
+          lR[q] = ldc<COH>(rho + n);
+          lU[q] = ldc<COH>(uxa + n);
+          lV[q] = ldc<COH>(uya + n);
         }
       } else if (j == nT && top_open) {
         const size_t n = (size_t)(P.ny - 1) * nx + gx;
-        lU[q] = uxa[n];
-        lV[q] = uya[n];
+        lU[q] = ldc<COH>(uxa + n);
+        lV[q] = ldc<COH>(uya + n);
       }
     }
   }
@@ -364,7 +371,7 @@ __device__ __forceinline__ void energy_rows_tile(
   }
 }
 
-template <int NW, int B>
+template <int NW, int B, bool COH = false>
 __device__ __forceinline__ void energy_rows_step(
     const KParams& P, const float* __restrict__ Tin, float* __restrict__ Tout,
     const float* __restrict__ rho, const float* __restrict__ uxa, const float* __restrict__ uya,
@@ -378,12 +385,11 @@ __device__ __forceinline__ void energy_rows_step(
   const bool plain_tile = (j0 - 4 >= P.nh) && (j0 + TY + 3 <= nT - 1) &&
                           !(P.flags & (NO_ADVECTION | NO_LATENT));
   if (plain_tile)
-    energy_rows_tile<NW, B, true>(P, sh, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
-                                  tile, x0, j0, TY);
+    energy_rows_tile<NW, B, true, COH>(P, sh, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
+                                       tile, x0, j0, TY);
   else
-    energy_rows_tile<NW, B, false>(P, sh, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
-                                   tile, x0, j0, TY);
-
+    energy_rows_tile<NW, B, false, COH>(P, sh, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd,
+                                        dstep_prev, tile, x0, j0, TY);
 }
 
 template <int NW, int B, int WPE>
@@ -402,6 +408,96 @@ __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WP
   }
   energy_rows_step<NW, B>(P, Tin, Tout, rho, uxa, uya, hist_slot, diag, sub, dtd, dstep_prev,
                           xcd_tile_edges_first(blockIdx.x - 1, P.nblkE));
+}
+
+// ---------------------------------------------------------------------------
+// Fused FP32 step (one energy sub-step): one launch per LB step.  Block b takes item
+// order[b] of a host-built order: first the collide items (item c runs collide tiles 2c
+// and 2c + 1, one per half of the workgroup), then the open-top block (item npair),
+// then the energy tiles (item npair + 1 + e), bottom-up.  A collide tile, once its
+// outputs are stored, records the step it completed in cdone[tile]; the outlet block and
+// each energy tile first wait until the collide tiles whose rows and columns they read
+// have completed this step, so an energy tile starts as soon as its own neighbourhood is
+// done, on the slot of a finished collide tile, without the launch boundary in between.
+// Collide tiles wait for nothing and precede every waiting block, so with in-order
+// dispatch every wait ends; a wait beyond its spin bound flags ERR_SYNC instead of
+// hanging.  What is produced and consumed inside the launch (rho, u, the top row's
+// populations, the collide partials) moves by agent-coherent loads and stores;
+// everything else crosses a kernel boundary.
+// ---------------------------------------------------------------------------
+constexpr int SPIN_MAX = 1 << 20;  // polls (each with a short sleep) before ERR_SYNC
+
+// Lane l (< 64, lane_on) of wave 0 waits until cdone of the collide tile in column
+// cx and each tile row ry0..ry1 has reached `want`; then the whole block synchronises.
+__device__ __forceinline__ void wait_collide_rows(const KParams& P, const unsigned* __restrict__ cdone,
+                                                  unsigned want, int ry0, int ry1, int cx, bool lane_on,
+                                                  DevDiag* __restrict__ diag, long long step) {
+  if (threadIdx.x < 64 && lane_on) {
+    for (int ry = ry0; ry <= ry1; ++ry) {
+      const unsigned* f = cdone + (size_t)ry * P.ntxL + cx;
+      int spins = 0;
+      while ((int)(ldc<true>(f) - want) < 0) {
+        if (++spins > SPIN_MAX) {
+          flag_error(diag, ERR_SYNC, step);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int TYC, int NWC, int NW, int B, int WPE>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
+    k_step_fused(const KParams P, const float* __restrict__ fsrc, float* __restrict__ fdst,
+                 float* __restrict__ topin, const float* __restrict__ Tin, float* __restrict__ Tout,
+                 const float* __restrict__ gw, float* __restrict__ rho, float* __restrict__ uxa,
+                 float* __restrict__ uya, const double* __restrict__ mstate_prev,
+                 const double* __restrict__ pmin_prev, double* __restrict__ mstate_cur,
+                 double* __restrict__ partL_cur, double* __restrict__ pmin_cur, DevDiag* __restrict__ diag,
+                 const long long* __restrict__ dstep_prev, long long* __restrict__ dstep_cur,
+                 double* __restrict__ hist_slot, unsigned* __restrict__ cdone,
+                 const int* __restrict__ order, double dtd) {
+  constexpr int HALVES = NW / NWC;  // collide tiles per workgroup
+  static_assert(HALVES * NWC == NW && (HALVES == 1 || HALVES == 2), "collide tiles per energy-sized workgroup");
+  const int b = __builtin_amdgcn_readfirstlane(order[blockIdx.x]);
+  const int npair = (P.nblkL + HALVES - 1) / HALVES;
+  const long long step = dstep_prev[0];  // index of this step (collide tile 0 writes the other slot)
+  const unsigned want = (unsigned)(step + 1);
+  if (b < npair) {
+    const int half = HALVES > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / (NWC * 64)) : 0;
+    const int tile = HALVES * b + half;  // == nblkL: an empty half
+    collide_tile<float, TYC, NWC, true, HALVES>(P, fsrc, fdst, topin, Tin, gw, rho, uxa, uya, mstate_prev,
+                                           pmin_prev, mstate_cur, partL_cur, diag, dstep_prev, dstep_cur, tile);
+    // every wave's stores complete before a tile is marked done
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if ((threadIdx.x % (NWC * 64)) == 0 && tile < P.nblkL) stc<true>(cdone + tile, want);
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  if (b == npair) {
+    // the open-top rule reads the top row's populations, u of the row below and the
+    // partials of that row's tiles: all collide tiles of the last two fluid rows
+    if (P.top_bc != TOP_WALL) {
+      const int ry0 = max(P.ny - 2, 0) / TYC, ry1 = (P.ny - 1) / TYC;
+      for (int c0 = 0; c0 < P.ntxL; c0 += 64)
+        wait_collide_rows(P, cdone, want, ry0, ry1, c0 + lane, c0 + lane < P.ntxL, diag, step);
+    }
+    outlet_block<float, NW, true>(P, fdst, topin, uxa, uya, partL_cur, pmin_cur);
+    return;
+  }
+  const int tile = b - npair - 1;
+  int j0, TY;
+  energy_tile_rows(P, tile, j0, TY);
+  const int x0 = (tile % P.ntxE) * P.txE;
+  // fluid rows whose rho and u the tile may read (its T rows with the four-row halo and
+  // one more each way), in the tile columns of the lanes' global columns
+  const int ylo = max(j0 - 5 - P.nh, 0), yhi = min(j0 + TY + 4 - P.nh, P.ny - 1);
+  if (yhi >= ylo)
+    wait_collide_rows(P, cdone, want, ylo / TYC, yhi / TYC, wrapm(x0 - 4 + lane, P.nx) / 64, true, diag, step);
+  energy_rows_step<NW, B, true>(P, Tin, Tout, rho, uxa, uya, hist_slot, diag, 0, dtd, dstep_prev, tile);
 }
 
 }  // namespace lbmk

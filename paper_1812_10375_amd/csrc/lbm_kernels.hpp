@@ -102,6 +102,21 @@ __device__ __forceinline__ void st32(T* __restrict__ base, unsigned i, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)) = v;
 }
 
+// Loads and stores of data that another workgroup of the same launch produces or
+// consumes (COH = true): agent-scope relaxed atomic accesses, coherent across the XCDs'
+// separate L2 caches without cache-wide write-back or invalidation.  With COH = false
+// they are plain accesses (the data crosses a kernel boundary).
+template <bool COH, typename T>
+__device__ __forceinline__ T ldc(const T* p) {
+  if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool COH, typename T>
+__device__ __forceinline__ void stc(T* p, T v) {
+  if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -486,7 +501,7 @@ constexpr int RED_SIZE = 128;
 //   convective outlet (Sec. 4.2): (f^n(top) + U f^{n+1}(top-1)) / (1 + U), where the new
 //   populations of the row below are pulled from the top row's post-collision values.
 // Returns the net mass change of the column: inflow minus the outflow of 2, 5, 6.
-template <typename real>
+template <typename real, bool COH>
 __device__ __forceinline__ double outlet_column(const KParams& P, int x, real U,
                                                 const real* __restrict__ fpost,
                                                 real* __restrict__ topin,
@@ -497,7 +512,7 @@ __device__ __forceinline__ double outlet_column(const KParams& P, int x, real U,
   const size_t below = (size_t)(ny - 2) * nx, top = (size_t)(ny - 1) * nx;
   real in4, in7, in8;
   if (P.top_bc == TOP_CONST_PRESSURE) {
-    const real r = (real)P.rho_v, ux = uxa[below + x], uy = uya[below + x];
+    const real r = (real)P.rho_v, ux = ldc<COH>(uxa + below + x), uy = ldc<COH>(uya + below + x);
     const real usq = real(1.5) * (ux * ux + uy * uy);
     const real w1 = r / real(9), w2 = r / real(36);
     const real e4 = -uy, e7 = -ux - uy, e8 = ux - uy;
@@ -507,15 +522,16 @@ __device__ __forceinline__ double outlet_column(const KParams& P, int x, real U,
   } else {
     const real inv = real(1) / (real(1) + U);
     const int xm = wrap1(x - 1, nx), xp = wrap1(x + 1, nx);
-    in4 = (topin[x] + U * fpost[4 * N + top + x]) * inv;
-    in7 = (topin[nx + x] + U * fpost[7 * N + top + xp]) * inv;
-    in8 = (topin[2 * nx + x] + U * fpost[8 * N + top + xm]) * inv;
+    in4 = (topin[x] + U * ldc<COH>(fpost + 4 * N + top + x)) * inv;
+    in7 = (topin[nx + x] + U * ldc<COH>(fpost + 7 * N + top + xp)) * inv;
+    in8 = (topin[2 * nx + x] + U * ldc<COH>(fpost + 8 * N + top + xm)) * inv;
   }
   topin[x] = in4;
   topin[nx + x] = in7;
   topin[2 * nx + x] = in8;
   // populations 2, 5, 6 of the top row leave through the opening
-  const real out = (fpost[2 * N + top + x] + fpost[5 * N + top + x]) + fpost[6 * N + top + x];
+  const real out = (ldc<COH>(fpost + 2 * N + top + x) + ldc<COH>(fpost + 5 * N + top + x)) +
+                   ldc<COH>(fpost + 6 * N + top + x);
   return (((double)in4 + (double)in7) + (double)in8) - (double)out;
 }
 
@@ -526,7 +542,12 @@ __device__ __forceinline__ double outlet_column(const KParams& P, int x, real U,
 //   phase 2  forces (Eq. 6, 9, 10), velocity (Eq. 5), MRT collision (Eq. 2, 8);
 //            write f*^n, rho, u; FP64 partial of the mass that the next pull sees.
 // ---------------------------------------------------------------------------
-template <typename real, int TY>
+// NW waves (64 NW threads) per tile.  A workgroup of HALVES x 64 NW threads runs HALVES
+// tiles side by side (one per group of NW waves, `tile` being that group's tile; a tile
+// index >= nblkL is an empty tile that only takes part in the barriers).  COH: the
+// tile's outputs are read by other workgroups of the same launch (the fused step), so
+// they are stored coherently.
+template <typename real, int TY, int NW, bool COH, int HALVES = 1>
 __device__ __forceinline__ void collide_tile(
     const KParams& P, const real* __restrict__ fsrc, real* __restrict__ fdst,
     const real* __restrict__ topin, const real* __restrict__ Tcur, const real* __restrict__ gw,
@@ -534,12 +555,19 @@ __device__ __forceinline__ void collide_tile(
     const double* __restrict__ mstate_prev, const double* __restrict__ pmin_prev,
     double* __restrict__ mstate_cur, double* __restrict__ partL_out, DevDiag* __restrict__ diag,
     const long long* __restrict__ dstep_prev, long long* __restrict__ dstep_cur, int tile) {
-  constexpr int RPT = TY / 4;  // rows per thread
+  static_assert(TY % NW == 0 && NW <= 16, "rows of a collide tile per wave");
+  constexpr int RPT = TY / NW;  // rows per thread
+  constexpr int NTH = NW * 64;
   constexpr int LW = 66;
-  __shared__ real spsi[TY + 2][LW];
-  __shared__ double red[RED_SIZE];
+  __shared__ real spsi_all[HALVES][TY + 2][LW];
+  __shared__ double red_all[HALVES][RED_SIZE];
+  const int half = HALVES > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / NTH) : 0;
+  real(*spsi)[LW] = spsi_all[half];
+  double* red = red_all[half];
+  const bool live = tile < P.nblkL;
+  if (!live) tile = 0;  // an empty tile: rows beyond the grid, no outputs
 
-  const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int t = (int)threadIdx.x - half * NTH, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
 
@@ -552,7 +580,7 @@ __device__ __forceinline__ void collide_tile(
     for (int b = 0; b < P.ntxE; ++b) mnow += pmin_prev[b];
   }
 
-  const int x0 = (tile % P.ntxL) * 64, y0 = (tile / P.ntxL) * TY;
+  const int x0 = (tile % P.ntxL) * 64, y0 = live ? (tile / P.ntxL) * TY : ny + 1;
   unsigned err = 0;
 
   real f[RPT][9];
@@ -560,7 +588,7 @@ __device__ __forceinline__ void collide_tile(
   const int gxo = wrapm(x0 + lane, nx);
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int ly = wv + 4 * k, y = y0 + ly;
+    const int ly = wv + NW * k, y = y0 + ly;
     real ps = real(0);
     if (y < ny) {
       pull(fsrc, topin, gxo, y, nx, ny, N, P.top_bc, f[k]);
@@ -575,7 +603,7 @@ __device__ __forceinline__ void collide_tile(
     spsi[ly + 1][lane + 1] = ps;
   }
   // ring of the tile: 66 + 66 + TY + TY cells
-  for (int c = t; c < 2 * LW + 2 * TY; c += NT) {
+  for (int c = t; c < 2 * LW + 2 * TY; c += NTH) {
     int lx, ly;
     if (c < LW) { lx = c - 1; ly = -1; }
     else if (c < 2 * LW) { lx = c - LW - 1; ly = TY; }
@@ -600,7 +628,7 @@ __device__ __forceinline__ void collide_tile(
   const long long step = dstep_prev[0];
   if (t == 0) {
     red[112] = mnow;
-    if (tile == 0) {
+    if (live && tile == 0) {
       mstate_cur[0] = mnow;
       dstep_cur[0] = step + 1;
     }
@@ -623,7 +651,7 @@ __device__ __forceinline__ void collide_tile(
 
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int ly = wv + 4 * k, y = y0 + ly;
+    const int ly = wv + NW * k, y = y0 + ly;
     if (y >= ny || x0 + lane >= nx) continue;
     const int cx = lane + 1, cy = ly + 1;
     const real pc = spsi[cy][cx];
@@ -668,10 +696,10 @@ __device__ __forceinline__ void collide_tile(
     }
     const size_t n = (size_t)y * nx + gxo;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fdst[i * N + n] = f[k][i];
-    rho_out[n] = r;
-    ux_out[n] = ux;
-    uy_out[n] = uy;
+    for (int i = 0; i < 9; ++i) stc<COH>(fdst + i * N + n, f[k][i]);
+    stc<COH>(rho_out + n, r);
+    stc<COH>(ux_out + n, ux);
+    stc<COH>(uy_out + n, uy);
     // post-collision mass (per node in the field precision, accumulated in FP64); the
     // open top's net exchange is added by the outlet block of the energy launch
     const real ms = ((f[k][0] + f[k][1]) + (f[k][2] + f[k][3])) + ((f[k][4] + f[k][5]) + (f[k][6] + f[k][7])) + f[k][8];
@@ -697,7 +725,7 @@ __device__ __forceinline__ void collide_tile(
     __syncthreads();
     if (t == 0) {
       double a = red[0], b = red[1];
-      for (int q = 1; q < NT / 64; ++q) {
+      for (int q = 1; q < NW; ++q) {
         a += red[2 * q];
         b += red[2 * q + 1];
       }
@@ -708,17 +736,19 @@ __device__ __forceinline__ void collide_tile(
     double vm = wave_max((double)umax2);
     __syncthreads();
     if (lane == 0) red[96 + wv] = vm;
-    block_sum_n<2, NT / 64>(v, red);
+    block_sum_n<2, NW>(v, red);
   }
-  if (t == 0) {
-    partL_out[3 * tile] = v[0];
-    partL_out[3 * tile + 1] = fmax(fmax(red[96], red[97]), fmax(red[98], red[99]));
-    partL_out[3 * tile + 2] = v[1];
+  if (t == 0 && live) {
+    double m = red[96];
+    for (int q = 1; q < NW; ++q) m = fmax(m, red[96 + q]);
+    stc<COH>(partL_out + 3 * tile, v[0]);
+    stc<COH>(partL_out + 3 * tile + 1, m);
+    stc<COH>(partL_out + 3 * tile + 2, v[1]);
   }
 }
 
-template <typename real, int TY>
-__global__ void __launch_bounds__(NT)
+template <typename real, int TY, int NW>
+__global__ void __launch_bounds__(NW * 64)
     k_collide(const KParams P, const real* __restrict__ fsrc, real* __restrict__ fdst,
               const real* __restrict__ topin, const real* __restrict__ Tcur,
               const real* __restrict__ gw, real* __restrict__ rho_out, real* __restrict__ ux_out,
@@ -726,8 +756,9 @@ __global__ void __launch_bounds__(NT)
               const double* __restrict__ pmin_prev, double* __restrict__ mstate_cur,
               double* __restrict__ partL_out, DevDiag* __restrict__ diag,
               const long long* __restrict__ dstep_prev, long long* __restrict__ dstep_cur) {
-  collide_tile<real, TY>(P, fsrc, fdst, topin, Tcur, gw, rho_out, ux_out, uy_out, mstate_prev, pmin_prev,
-                         mstate_cur, partL_out, diag, dstep_prev, dstep_cur, xcd_tile(blockIdx.x, P.nblkL));
+  collide_tile<real, TY, NW, false>(P, fsrc, fdst, topin, Tcur, gw, rho_out, ux_out, uy_out, mstate_prev,
+                                    pmin_prev, mstate_cur, partL_out, diag, dstep_prev, dstep_cur,
+                                    xcd_tile(blockIdx.x, P.nblkL));
 }
 
 // ---------------------------------------------------------------------------
@@ -1068,7 +1099,7 @@ __device__ __forceinline__ void energy_lds_tile(
 // the net inflow of each energy tile column (FP64, lanes summed in a fixed order).  Run
 // by one whole workgroup of NW waves beside the tiles of the energy launch, once per LB
 // step, so that its chain of dependent loads does not lengthen any tile.
-template <typename real, int NW>
+template <typename real, int NW, bool COH = false>
 __device__ __forceinline__ void outlet_block(const KParams& P, const real* __restrict__ fpost,
                                              real* __restrict__ topin, const real* __restrict__ uxa,
                                              const real* __restrict__ uya, const double* __restrict__ partL_cur,
@@ -1085,7 +1116,7 @@ __device__ __forceinline__ void outlet_block(const KParams& P, const real* __res
       // mean outflow velocity of the row below the top, from the collide partials
       const int ry = (P.ny - 2) / P.tyL;
       double us = 0.0;
-      for (int bx = 0; bx < P.ntxL; ++bx) us += partL_cur[3 * (ry * P.ntxL + bx) + 2];
+      for (int bx = 0; bx < P.ntxL; ++bx) us += ldc<COH>(partL_cur + 3 * (ry * P.ntxL + bx) + 2);
       us /= P.nx;
       uo = us > 0.0 ? us : 0.0;
     }
@@ -1095,7 +1126,7 @@ __device__ __forceinline__ void outlet_block(const KParams& P, const real* __res
   for (int b = w; b < P.ntxE; b += NW) {
     const int x = b * P.txE + lane;
     double d = 0.0;
-    if (lane < P.txE && x < P.nx) d = outlet_column(P, x, U, fpost, topin, uxa, uya);
+    if (lane < P.txE && x < P.nx) d = outlet_column<real, COH>(P, x, U, fpost, topin, uxa, uya);
     d = wave_sum(d);
     if (lane == 0) pmin_cur[b] = d;
   }

@@ -50,16 +50,36 @@ void step_once(lbm_ctx* h) {
   DevDiag* diag = h->at<DevDiag>(L.diag);
   const real* gw = h->at<real>(L.gw);
   const real* Tc = h->at<real>(L.T[h->tcur]);
+  const double dt = 1.0 / h->cfg.n_sub;
+  const bool iso = (h->cfg.flags & LBM_DIFF_ISOTROPIC) != 0;
+  double* hslot = h->at<double>(L.hist) + (size_t)((h->hist_first + h->hist_count) % HIST) * P.nblkE * 5;
+  if constexpr (!f64) {
+    if (h->fused) {
+      // the whole step in one launch: collide tile pairs, the outlet block, energy tiles
+      const int tev = timing_begin(h, 0);
+      hipLaunchKernelGGL((lbmk::k_step_fused<TY_F32, NWC, E_RNW, E_BAND, E_RWPE>),
+                         dim3((P.nblkL + 1) / 2 + 1 + P.nblkE),
+                         dim3(E_RNW * 64), 0, h->stream, P, fs, fd, topin, Tc, h->at<real>(L.T[1 - h->tcur]), gw,
+                         rho, ux, uy, h->at<double>(L.mstate[prev]), h->at<double>(L.pmin[prev]),
+                         h->at<double>(L.mstate[cur]), h->at<double>(L.partL[cur]), h->at<double>(L.pmin[cur]),
+                         diag, h->at<long long>(L.dstep[prev]), h->at<long long>(L.dstep[cur]), hslot,
+                         h->at<unsigned>(L.cdone), h->at<int>(L.order), dt);
+      timing_end(h, tev);
+      h->tcur = 1 - h->tcur;
+      h->hist_count += 1;
+      h->fcur = 1 - h->fcur;
+      h->step += 1;
+      if (h->hist_count == HIST) finish_reductions<real>(h);
+      return;
+    }
+  }
   int tev = timing_begin(h, 0);
-  hipLaunchKernelGGL((lbmk::k_collide<real, f64 ? TY_F64 : TY_F32>), dim3(P.nblkL), dim3(NT), 0,
+  hipLaunchKernelGGL((lbmk::k_collide<real, f64 ? TY_F64 : TY_F32, NWC>), dim3(P.nblkL), dim3(NWC * 64), 0,
                      h->stream, P, fs, fd, topin, Tc, gw, rho, ux, uy, h->at<double>(L.mstate[prev]),
                      h->at<double>(L.pmin[prev]), h->at<double>(L.mstate[cur]),
                      h->at<double>(L.partL[cur]), diag, h->at<long long>(L.dstep[prev]),
                      h->at<long long>(L.dstep[cur]));
   timing_end(h, tev);
-  const double dt = 1.0 / h->cfg.n_sub;
-  const bool iso = (h->cfg.flags & LBM_DIFF_ISOTROPIC) != 0;
-  double* hslot = h->at<double>(L.hist) + (size_t)((h->hist_first + h->hist_count) % HIST) * P.nblkE * 5;
   for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
     const real* Tin = h->at<real>(L.T[h->tcur]);
     real* Tout = h->at<real>(L.T[1 - h->tcur]);
@@ -115,7 +135,7 @@ void batch_step_once(lbm_batch* b) {
   int tcur = h0->tcur;
   const int hslot = (h0->hist_first + h0->hist_count) % HIST;
   const bool iso = (h0->cfg.flags & LBM_DIFF_ISOTROPIC) != 0;
-  hipLaunchKernelGGL((lbmk::k_collide_batch<real, f64 ? TY_F64 : TY_F32>), dim3(b->nblkL), dim3(NT), 0,
+  hipLaunchKernelGGL((lbmk::k_collide_batch<real, f64 ? TY_F64 : TY_F32, NWC>), dim3(b->nblkL), dim3(NWC * 64), 0,
                      b->stream, b->table, n, fcur, tcur, cur);
   const double dt = 1.0 / h0->cfg.n_sub;
   for (int sub = 0; sub < h0->cfg.n_sub; ++sub) {
@@ -149,6 +169,9 @@ int scatter_state(lbm_ctx* h, const real* src, int src_is_rho) {
   const int last = (int)((h->step + 1) & 1);
   if (hipMemsetAsync(h->at<double>(L.pmin[last]), 0, (size_t)h->P.ntxE * sizeof(double), h->stream) !=
       hipSuccess)
+    return LBM_EHIP;
+  // the fused step's completion marks restart with the step count (they only grow)
+  if (hipMemsetAsync(h->at<unsigned>(L.cdone), 0, (size_t)h->P.nblkL * sizeof(unsigned), h->stream) != hipSuccess)
     return LBM_EHIP;
   hipLaunchKernelGGL((lbmk::k_scatter<real>), dim3(h->P.nblkL), dim3(NT), 0, h->stream, h->P, src,
                      src_is_rho, h->at<real>(L.f[h->fcur]), h->at<real>(L.topin),

@@ -8,7 +8,7 @@ namespace lbmk {
 enum { TOP_WALL = 0, TOP_CONST_PRESSURE = 1, TOP_CONVECTIVE = 2 };
 enum { TBC_DIRICHLET = 0, TBC_FLUX = 1, TBC_ZERO_GRAD = 2 };
 enum { FREEZE_EOS_T = 1, NO_ADVECTION = 2, NO_LATENT = 4, DIFF_ISOTROPIC = 8 };
-enum { ERR_RHO = 1, ERR_COVOLUME = 2, ERR_RADICAND = 4, ERR_NONFINITE = 8 };
+enum { ERR_RHO = 1, ERR_COVOLUME = 2, ERR_RADICAND = 4, ERR_NONFINITE = 8, ERR_SYNC = 16 };
 
 constexpr int NT = 256;  // threads per block in every kernel
 
@@ -42,7 +42,8 @@ struct DevDiag {
 
 // Byte offsets of the arrays carved out of a domain's workspace.
 struct Layout {
-  size_t f[2], T[2], rho, ux, uy, topin, gw, partL[2], pmin[2], mstate[2], dstep[2], hist, steps, diag, total;
+  size_t f[2], T[2], rho, ux, uy, topin, gw, partL[2], pmin[2], mstate[2], dstep[2], hist, steps, diag, cdone, order,
+      total;
 };
 
 // One domain of a batch, as the batched kernels see it (device memory).  tile0L and

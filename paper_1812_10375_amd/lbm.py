@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
 F32, F64 = 0, 1
 TOP_BC = {"wall": 0, "const_pressure": 1, "convective": 2}
 TBC = {"dirichlet": 0, "flux": 1, "zero_grad": 2}
-FLAG_BITS = {"freeze_eos_T": 1, "no_advection": 2, "no_latent": 4, "diff_isotropic": 8}
+FLAG_BITS = {"freeze_eos_T": 1, "no_advection": 2, "no_latent": 4, "diff_isotropic": 8,
+             "two_launches": 32, "one_launch": 64}
 FIELDS = {"f": 0, "rho": 1, "ux": 2, "uy": 3, "T": 4, "Gw": 10}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
           -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}

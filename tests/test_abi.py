@@ -52,7 +52,7 @@ def test_workspace_bytes_for_the_full_boiling_workload():
 @pytest.mark.parametrize("change", [
     {"nx": 0}, {"ny": 0}, {"n_sub": 0}, {"heater_rows": -1}, {"precision": "f16"},
     {"ny": 1, "top_bc": "convective"}, {"G": 1.0}, {"tau_l": 0.5}, {"s_q": 2.0},
-    {"rho_v": 7.0}, {"k": 0.0}, {"g": float("nan")},
+    {"rho_v": 7.0}, {"k": 0.0}, {"g": float("nan")}, {"flags": ("two_launches", "one_launch")},
 ])
 def test_invalid_configurations_are_rejected(change):
     sc = S.film_evaporation(nx=16, ny=16, film=4)
