@@ -153,9 +153,21 @@ enum { LBM_ERR_RHO = 1, LBM_ERR_COVOLUME = 2, LBM_ERR_RADICAND = 4, LBM_ERR_NONF
  *   LBM_FIELD_T    (heater_rows + ny) x nx temperature                     read/write
  *   LBM_FIELD_RHO  ny x nx density of the last collision                   read
  *   LBM_FIELD_UX/UY ny x nx Eq. 5 velocity of the last collision           read
- *   LBM_FIELD_GW   nx wall strength of each column of the bottom wall      read       */
+ *   LBM_FIELD_GW   nx wall strength of each column of the bottom wall      read
+ *   LBM_FIELD_STATE the rest of the state a run continues from, as an opaque record of
+ *                  lbm_field_bytes() bytes (host memory only): the step count, the mass
+ *                  carried by continuity and the last step's exchange through an open
+ *                  top (which set rho_ave of the next step, Eq. 9), the cumulative heat
+ *                  and energy sums, the running statistics of the bottom heat flux and
+ *                  the sticky error state.                                     read/write
+ * Checkpoint: lbm_read_field of F, T and STATE (reading STATE folds the pending
+ * diagnostics as lbm_observe does).  Restart, in a context of the same configuration:
+ * lbm_write_field of F, then T, then STATE (writing F resets the step count and the
+ * carried mass; STATE, written last, restores them).  The run then continues bitwise
+ * as if it had not been interrupted, its observations included.  A batch domain's STATE
+ * can be read but not written (the domains of a batch share one step count). */
 enum { LBM_FIELD_F = 0, LBM_FIELD_RHO = 1, LBM_FIELD_UX = 2, LBM_FIELD_UY = 3, LBM_FIELD_T = 4,
-       LBM_FIELD_GW = 10 };
+       LBM_FIELD_GW = 10, LBM_FIELD_STATE = 11 };
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -194,8 +206,13 @@ int lbm_observe(lbm_ctx *h, lbm_obs *out);
  * field's size).  Synchronises the stream for host destinations. */
 int lbm_read_field(lbm_ctx *h, int field, void *dst, size_t bytes, int dst_is_device);
 
-/* Overwrite the populations (LBM_FIELD_F, pre-collision) or the temperature. */
+/* Overwrite the populations (LBM_FIELD_F, pre-collision), the temperature or the run
+ * state (LBM_FIELD_STATE, host memory; LBM_EINVAL if the record does not belong to this
+ * configuration). */
 int lbm_write_field(lbm_ctx *h, int field, const void *src, size_t bytes, int src_is_device);
+
+/* Size in bytes of a field of this context (0 for an unknown field). */
+size_t lbm_field_bytes(lbm_ctx *h, int field);
 
 /* Per-kernel timing for measurement.  While enabled, lbm_step records HIP events on
  * the context's stream around the collide kernel and around the energy kernel(s) of

@@ -418,8 +418,119 @@ int lbm_observe(lbm_ctx* h, lbm_obs* out) {
   return read_observation(h, out);
 }
 
+}  // extern "C"
+
+namespace {
+
+// The run state beyond the fields (LBM_FIELD_STATE), as a host record: a header that
+// identifies the configuration, the device diagnostics and the carried mass, followed
+// by the per-column exchange through the open top of the last step (ntxE doubles) and
+// the last collision's per-tile partials (3 nblkL doubles: post-collision mass, largest
+// |u|^2, sum of u_y on row ny - 2), from which an observation sums the current mass.
+constexpr uint64_t STATE_MAGIC = 0x3154415453424c4dull;  // "MLBSTAT1"
+struct StateRecord {
+  uint64_t magic;
+  int64_t step;
+  int32_t nx, ny, nh, ntxE, nblkL;
+  int32_t precision;
+  lbmk::DevDiag diag;
+  double mass_carried;
+};
+
+size_t state_bytes(const lbm_ctx* h) {
+  return sizeof(StateRecord) + ((size_t)h->P.ntxE + 3 * (size_t)h->P.nblkL) * sizeof(double);
+}
+
+int read_state(lbm_ctx* h, void* dst) {
+  if (h->hist_count > 0) {  // fold the pending diagnostics first
+    if (h->cfg.precision == LBM_F64) finish_reductions<double>(h);
+    else finish_reductions<float>(h);
+  }
+  const Layout& L = h->L;
+  const int last = (int)((h->step + 1) & 1);
+  StateRecord r{};
+  long long dstep = 0;
+  std::vector<double> pm((size_t)h->P.ntxE), pl(3 * (size_t)h->P.nblkL);
+  if (hipMemcpyAsync(&r.diag, h->at<DevDiag>(L.diag), sizeof(DevDiag), hipMemcpyDeviceToHost, h->stream) ||
+      hipMemcpyAsync(&r.mass_carried, h->at<double>(L.mstate[last]), sizeof(double), hipMemcpyDeviceToHost,
+                     h->stream) ||
+      hipMemcpyAsync(pm.data(), h->at<double>(L.pmin[last]), pm.size() * sizeof(double), hipMemcpyDeviceToHost,
+                     h->stream) ||
+      hipMemcpyAsync(pl.data(), h->at<double>(L.partL[last]), pl.size() * sizeof(double), hipMemcpyDeviceToHost,
+                     h->stream) ||
+      hipMemcpyAsync(&dstep, h->at<long long>(L.dstep[last]), sizeof(dstep), hipMemcpyDeviceToHost, h->stream) ||
+      hipStreamSynchronize(h->stream))
+    return LBM_EHIP;
+  r.magic = STATE_MAGIC;
+  r.step = dstep;
+  r.nx = h->cfg.nx;
+  r.ny = h->cfg.ny;
+  r.nh = h->cfg.heater_rows;
+  r.ntxE = h->P.ntxE;
+  r.nblkL = h->P.nblkL;
+  r.precision = h->cfg.precision;
+  char* out = static_cast<char*>(dst);
+  std::memcpy(out, &r, sizeof(r));
+  std::memcpy(out + sizeof(r), pm.data(), pm.size() * sizeof(double));
+  std::memcpy(out + sizeof(r) + pm.size() * sizeof(double), pl.data(), pl.size() * sizeof(double));
+  return LBM_OK;
+}
+
+int write_state(lbm_ctx* h, const void* src) {
+  StateRecord r;
+  std::memcpy(&r, src, sizeof(r));
+  if (r.magic != STATE_MAGIC || r.nx != h->cfg.nx || r.ny != h->cfg.ny || r.nh != h->cfg.heater_rows ||
+      r.ntxE != h->P.ntxE || r.nblkL != h->P.nblkL || r.precision != h->cfg.precision || r.step < 0)
+    return LBM_EINVAL;
+  const Layout& L = h->L;
+  h->step = r.step;
+  const int last = (int)((h->step + 1) & 1);
+  h->step_staging = (long long)r.step;
+  const double* pm = reinterpret_cast<const double*>(static_cast<const char*>(src) + sizeof(r));
+  const double* pl = pm + r.ntxE;
+  if (hipMemcpyAsync(h->at<double>(L.partL[last]), pl, 3 * (size_t)r.nblkL * sizeof(double), hipMemcpyHostToDevice,
+                     h->stream))
+    return LBM_EHIP;
+  if (hipMemcpyAsync(h->at<DevDiag>(L.diag), &r.diag, sizeof(DevDiag), hipMemcpyHostToDevice, h->stream) ||
+      hipMemcpyAsync(h->at<double>(L.mstate[last]), &r.mass_carried, sizeof(double), hipMemcpyHostToDevice,
+                     h->stream) ||
+      hipMemcpyAsync(h->at<double>(L.pmin[last]), pm, (size_t)r.ntxE * sizeof(double), hipMemcpyHostToDevice,
+                     h->stream) ||
+      hipMemcpyAsync(h->at<long long>(L.dstep[last]), &h->step_staging, sizeof(long long), hipMemcpyHostToDevice,
+                     h->stream) ||
+      hipStreamSynchronize(h->stream))
+    return LBM_EHIP;
+  h->hist_count = 0;
+  h->bad = r.diag.err != 0;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_field_bytes(lbm_ctx* h, int field) {
+  if (!h) return 0;
+  const size_t R = h->cfg.precision == LBM_F64 ? 8 : 4;
+  const size_t nx = h->cfg.nx, N = nx * h->cfg.ny;
+  switch (field) {
+    case LBM_FIELD_F: return 9 * N * R;
+    case LBM_FIELD_RHO:
+    case LBM_FIELD_UX:
+    case LBM_FIELD_UY: return N * R;
+    case LBM_FIELD_T: return (N + nx * h->cfg.heater_rows) * R;
+    case LBM_FIELD_GW: return nx * R;
+    case LBM_FIELD_STATE: return state_bytes(h);
+    default: return 0;
+  }
+}
+
 int lbm_read_field(lbm_ctx* h, int field, void* dst, size_t bytes, int dst_is_device) {
   if (!h || !dst) return LBM_EINVAL;
+  if (field == LBM_FIELD_STATE) {
+    if (dst_is_device || bytes != state_bytes(h)) return LBM_EINVAL;
+    return read_state(h, dst);
+  }
   const Layout& L = h->L;
   const size_t R = h->cfg.precision == LBM_F64 ? 8 : 4;
   const size_t nx = h->cfg.nx, ny = h->cfg.ny, N = nx * ny;
@@ -452,6 +563,10 @@ int lbm_read_field(lbm_ctx* h, int field, void* dst, size_t bytes, int dst_is_de
 
 int lbm_write_field(lbm_ctx* h, int field, const void* src, size_t bytes, int src_is_device) {
   if (!h || !src) return LBM_EINVAL;
+  if (field == LBM_FIELD_STATE) {
+    if (src_is_device || bytes != state_bytes(h)) return LBM_EINVAL;
+    return write_state(h, src);
+  }
   const Layout& L = h->L;
   const size_t R = h->cfg.precision == LBM_F64 ? 8 : 4;
   const size_t nx = h->cfg.nx, ny = h->cfg.ny, N = nx * ny;
@@ -646,12 +761,15 @@ int lbm_batch_observe(lbm_batch* b, lbm_obs* out) {
 
 int lbm_batch_read_field(lbm_batch* b, int i, int field, void* dst, size_t bytes, int dst_is_device) {
   if (!b || i < 0 || i >= (int)b->dom.size()) return LBM_EINVAL;
+  // the domains share the diagnostics history: fold it for all (lbm_batch_observe) first
+  if (field == LBM_FIELD_STATE && b->dom[i]->hist_count != 0) return LBM_ESTATE;
   return lbm_read_field(b->dom[i], field, dst, bytes, dst_is_device);
 }
 
 int lbm_batch_write_field(lbm_batch* b, int i, int field, const void* src, size_t bytes, int src_is_device) {
   if (!b || i < 0 || i >= (int)b->dom.size()) return LBM_EINVAL;
   if (b->dom[i]->hist_count != 0) return LBM_ESTATE;  // call lbm_batch_observe first
+  if (field == LBM_FIELD_STATE) return LBM_EINVAL;     // the domains share one step count
   return lbm_write_field(b->dom[i], field, src, bytes, src_is_device);
 }
 

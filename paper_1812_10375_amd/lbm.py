@@ -17,7 +17,7 @@ TOP_BC = {"wall": 0, "const_pressure": 1, "convective": 2}
 TBC = {"dirichlet": 0, "flux": 1, "zero_grad": 2}
 FLAG_BITS = {"freeze_eos_T": 1, "no_advection": 2, "no_latent": 4, "diff_isotropic": 8,
              "two_launches": 32, "one_launch": 64}
-FIELDS = {"f": 0, "rho": 1, "ux": 2, "uy": 3, "T": 4, "Gw": 10}
+FIELDS = {"f": 0, "rho": 1, "ux": 2, "uy": 3, "T": 4, "Gw": 10, "state": 11}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
           -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
 ABI_VERSION = 2
@@ -75,6 +75,8 @@ def library():
         L.lbm_read_field.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
         L.lbm_write_field.restype = C.c_int
         L.lbm_write_field.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
+        L.lbm_field_bytes.restype = C.c_size_t
+        L.lbm_field_bytes.argtypes = [vp, C.c_int]
         L.lbm_destroy.restype = C.c_int
         L.lbm_destroy.argtypes = [vp]
         L.lbm_set_stream.restype = C.c_int
@@ -239,6 +241,40 @@ class Lattice:
                                        arr.nbytes, 0)
         if rc != 0:
             raise LbmError(rc, "lbm_write_field")
+
+    def read_state(self):
+        """The run state beyond the fields (LBM_FIELD_STATE) as raw bytes."""
+        n = library().lbm_field_bytes(self.h, FIELDS["state"])
+        out = np.zeros(n, dtype=np.uint8)
+        rc = library().lbm_read_field(self.h, FIELDS["state"], out.ctypes.data_as(C.c_void_p), n, 0)
+        if rc != 0:
+            raise LbmError(rc, "lbm_read_field(state)")
+        return out
+
+    def write_state(self, rec):
+        rec = np.ascontiguousarray(rec, dtype=np.uint8)
+        rc = library().lbm_write_field(self.h, FIELDS["state"], rec.ctypes.data_as(C.c_void_p), rec.nbytes, 0)
+        if rc != 0:
+            raise LbmError(rc, "lbm_write_field(state)")
+
+    def checkpoint(self):
+        """Everything a run continues from: populations, temperature and run state, in
+        the field precision (a dict of host arrays)."""
+        out = {}
+        for name in ("f", "T"):
+            arr = np.empty(self._shape(name), dtype=self.dtype)
+            rc = library().lbm_read_field(self.h, FIELDS[name], arr.ctypes.data_as(C.c_void_p), arr.nbytes, 0)
+            if rc != 0:
+                raise LbmError(rc, "lbm_read_field")
+            out[name] = arr
+        out["state"] = self.read_state()
+        return out
+
+    def restore(self, ckpt):
+        """Continue from a checkpoint of a run of the same configuration."""
+        self.write("f", ckpt["f"])
+        self.write("T", ckpt["T"])
+        self.write_state(ckpt["state"])
 
 
 def _shape_of(sc, name):
