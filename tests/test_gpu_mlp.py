@@ -34,6 +34,64 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
 
 
+# Per-element error bounds of the GPU results against the FP64 oracle, derived from what
+# the GPU rounds and the oracle does not.  The oracle already takes the BF16 weights and
+# inputs; the GPU also rounds the hidden activations H1, H2 and the back-propagated
+# gradients dY, dZ2, dZ1 to BF16 (unit roundoff U_BF = 2^-8) before each layer product,
+# and accumulates the exact BF16 products in FP32 (gamma_K = K 2^-24 / (1 - K 2^-24)).
+# Propagating these to first order through the oracle's intermediate values, with
+# |gelu'| <= 1.13 and |gelu''| <= 0.8, gives a bound d per element; the tests allow 2 d
+# (second-order terms and the FP32 erf/exp, whose errors are 1e-6 of U_BF).
+U_BF = 2.0 ** -8
+U32 = 2.0 ** -24
+GELU1, GELU2 = 1.13, 0.8
+
+
+def _gamma(k):
+    return k * U32 / (1 - k * U32)
+
+
+def _forward_bounds(w, X):
+    p = M.unpack(w)
+    Y, (X, Z1, H1, Z2, H2) = M.forward(w, X)
+    aW1, aW2, aW3 = np.abs(p["W1"]), np.abs(p["W2"]), np.abs(p["W3"])
+    dZ1 = _gamma(4) * (np.abs(X) @ aW1 + np.abs(p["b1"]))
+    dH1 = GELU1 * dZ1 + U_BF * np.abs(H1)
+    dZ2 = dH1 @ aW2 + _gamma(128) * (np.abs(H1) @ aW2 + np.abs(p["b2"]))
+    dH2 = GELU1 * dZ2 + U_BF * np.abs(H2)
+    dY = dH2 @ aW3 + _gamma(128) * (np.abs(H2) @ aW3 + np.abs(p["b3"]))
+    return Y, (X, Z1, H1, Z2, H2), (dZ1, dH1, dZ2, dH2, dY)
+
+
+def _grad_bounds(w, X, T):
+    """Per-element bounds of every gradient block (oracle's layout)."""
+    p = M.unpack(w)
+    Y, (X, Z1, H1, Z2, H2), (eZ1, eH1, eZ2, eH2, eY) = _forward_bounds(w, X)
+    B = X.shape[0]
+    aW2, aW3 = np.abs(p["W2"]), np.abs(p["W3"])
+    dY = 2.0 * (Y - T) / B
+    edY = 2.0 * eY / B
+    edYb = edY + U_BF * np.abs(dY)
+    g3 = dY @ p["W3"].T
+    dZ2 = g3 * M.gelu_grad(Z2)
+    edZ2 = (edYb @ aW3.T) * np.abs(M.gelu_grad(Z2)) + np.abs(g3) * GELU2 * eZ2 + _gamma(16) * (np.abs(dY) @ aW3.T)
+    ed2b = edZ2 + U_BF * np.abs(dZ2)
+    g2 = dZ2 @ p["W2"].T
+    dZ1 = g2 * M.gelu_grad(Z1)
+    edZ1 = (ed2b @ aW2.T) * np.abs(M.gelu_grad(Z1)) + np.abs(g2) * GELU2 * eZ1 + _gamma(128) * (np.abs(dZ2) @ aW2.T)
+    ed1b = edZ1 + U_BF * np.abs(dZ1)
+    aX, aH1, aH2 = np.abs(X), np.abs(H1), np.abs(H2)
+    b = {
+        "W3": eH2.T @ np.abs(dY) + aH2.T @ edYb + _gamma(B) * (aH2.T @ np.abs(dY)),
+        "b3": edY.sum(0) + _gamma(B) * np.abs(dY).sum(0),
+        "W2": eH1.T @ np.abs(dZ2) + aH1.T @ ed2b + _gamma(B) * (aH1.T @ np.abs(dZ2)),
+        "b2": edZ2.sum(0) + _gamma(B) * np.abs(dZ2).sum(0),
+        "W1": aX.T @ ed1b + _gamma(B) * (aX.T @ np.abs(dZ1)),
+        "b1": edZ1.sum(0) + _gamma(B) * np.abs(dZ1).sum(0),
+    }
+    return M.pack(b)
+
+
 def _setup(members=4, B=256, seed=11):
     from paper_1812_10375_amd.mlp import MLPEnsemble
     rng = np.random.default_rng(seed)
@@ -47,27 +105,33 @@ def _setup(members=4, B=256, seed=11):
     return net, params, X, T
 
 
-def test_forward_matches_oracle():
+def test_forward_matches_oracle_element_by_element():
     net, params, X, T = _setup()
     Y = net.forward(X).cpu().numpy().astype(np.float64)
     for k in range(net.members):
-        Yo, _ = M.forward(_weights_as_products_see_them(params[k]), X)
-        e = _rel(Y[k], Yo)
-        log("[mlp] member %d forward rel err %.2e" % (k, e))
-        assert e < 1e-2, (k, e)
+        Yo, _, (_, _, _, _, dY) = _forward_bounds(_weights_as_products_see_them(params[k]), X)
+        err = np.abs(Y[k] - Yo)
+        ratio = (err / (2 * dY)).max()
+        log("[mlp] member %d forward: max|dY| %.2e, max err/bound %.3f, median bound/|Y| %.2e"
+            % (k, err.max(), ratio, np.median(dY / np.abs(Yo))))
+        assert np.all(err <= 2 * dY), (k, ratio)
+        assert _rel(Y[k], Yo) < 1e-2
 
 
-def test_gradients_match_oracle():
+def test_gradients_match_oracle_element_by_element():
     net, params, X, T = _setup()
     loss = net.backward(X, T).cpu().numpy()
     G = net.grads()
     for k in range(net.members):
-        lo, go = M.loss_and_grad(_weights_as_products_see_them(params[k]), X, T)
+        w = _weights_as_products_see_them(params[k])
+        lo, go = M.loss_and_grad(w, X, T)
+        bound = _grad_bounds(w, X, T)
         assert loss[k] == pytest.approx(lo, rel=2e-2)
         for name, a, b in BLOCKS:
-            e = _rel(G[k, a:b], go[a:b])
-            log("[mlp] member %d grad %s rel err %.2e" % (k, name, e))
-            assert e < 3e-2, (k, name, e)
+            err = np.abs(G[k, a:b] - go[a:b])
+            ratio = (err / (2 * bound[a:b] + 1e-30)).max()
+            log("[mlp] member %d grad %s: max err %.2e, max err/bound %.3f" % (k, name, err.max(), ratio))
+            assert np.all(err <= 2 * bound[a:b]), (k, name, ratio)
 
 
 def test_adam_update_matches_oracle():

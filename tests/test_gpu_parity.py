@@ -23,6 +23,15 @@ def _check64(sc, steps, tol=TOL64):
     assert og["mass"] == pytest.approx(oo["mass"], rel=tol)
     for k in ("dE_cum", "Q_bottom_cum", "Q_top_cum", "Q_surface_cum", "energy"):
         assert og[k] == pytest.approx(oo[k], rel=1e-10, abs=1e-12 * max(1.0, abs(oo["Q_bottom_cum"]))), k
+    # the per-step fluxes and their running mean and variance (time averages of Sec. 4.4)
+    qs = max(abs(oo["q_bottom_mean"]), abs(oo["q_bottom"]), 1e-300)
+    for k in ("q_bottom", "q_surface", "q_bottom_mean"):
+        assert og[k] == pytest.approx(oo[k], rel=1e-10, abs=1e-12 * qs), k
+    assert og["q_bottom_var"] == pytest.approx(oo["q_bottom_var"], rel=1e-8, abs=1e-12 * qs * qs)
+    # the library reports the rho_ave of Eq. 9 that the next step uses (the mass after
+    # this step over the fluid nodes); the oracle's record holds the one this step used
+    assert og["rho_ave"] == pytest.approx(oo["mass"] / (sc["nx"] * sc["ny"]), rel=tol)
+    assert og["max_speed"] == pytest.approx(oo["max_speed"], rel=1e-9, abs=1e-15)
     return res, e
 
 
@@ -58,6 +67,20 @@ def test_fp64_tall_domain_with_interior_tiles():
 def test_fp64_film_constant_pressure_top():
     sc = S.film_evaporation(nx=70, ny=50, film=12, superheat=0.05, seed=7, precision="f64")
     _check64(sc, 300)
+
+
+def test_fp64_film_evaporation_1000_steps():
+    # the 256 x 256 film-evaporation workload (Dirichlet wall, 40-row film, seeded
+    # perturbation, constant-pressure top) in FP64 over 1000 steps
+    sc = S.film_evaporation(precision="f64")
+    _check64(sc, 1000)
+
+
+def test_fp64_pool_boiling_cropped_1000_steps():
+    # the pool-boiling workload cropped to 256 x 256 (25-row heater, sites, gravity,
+    # convective outlet, 70% liquid) in FP64 over 1000 steps
+    sc = S.pool_boiling(nx=256, ny=256, n_sites=2, min_spacing=64, seed=3, precision="f64")
+    _check64(sc, 1000)
 
 
 @pytest.mark.parametrize("nx,ny,nh", [(1, 12, 0), (3, 2, 2), (65, 17, 1)])
@@ -149,6 +172,13 @@ def test_fp32_pool_boiling_full_size_first_steps():
     # benchmark times, against the oracle over its first steps
     sc = S.pool_boiling()
     _check32(sc, 20)
+
+
+def test_fp32_error_trajectory_pool_boiling_full_size():
+    # the full 1024 x 1024 + 25 workload (8 sites, 70% pool, convective outlet; the fused
+    # step at this size) against the oracle every 100 steps over the first 1000 steps
+    worst = _trajectory32(S.pool_boiling())
+    log("[parity] 1024 x 1024 + 25 worst max|drho|/rho_l over 1000 steps %.2e" % worst)
 
 
 def test_fp32_pool_boiling_4096_first_steps():
