@@ -118,15 +118,16 @@ def film_evaporation(nx=256, ny=256, film=40, superheat=0.05, seed=2, steps=2000
 def film_evaporation_flux(ratio=1.0, q=2e-4, nx=20, ny=100, film=50, wall=20, n_sub=5, precision="f64",
                           isotropic=False):
     """Film evaporation driven by a heat flux through a wall (Sec. 3.3): a wall of
-    ``wall`` rows with lambda_w = ratio * lambda_l (rho_w = rho_l, c_v,w = c_v) receives
-    q through its bottom; a liquid film of ``film`` rows lies on it, vapour above, with a
-    constant-pressure top at rho_v; neutral wall, no gravity, everything starts at T_s.
-    ``n_sub`` energy sub-steps per LB step (Eq. 27) keep the RK4 update stable in the
-    more conductive walls.  The default sizes are the paper's (20 x 120 with the wall)."""
+    ``wall`` rows with rho_w = 3 rho_l, c_v,w = c_v and lambda_w = ratio * lambda_l
+    receives q through its bottom; a liquid film of ``film`` rows lies on it, vapour
+    above, with a constant-pressure top at rho_v; neutral wall, no gravity, everything
+    starts at T_s.  ``n_sub`` energy sub-steps per LB step (Eq. 27) keep the RK4 update
+    stable in the more conductive walls.  The default sizes are the paper's (20 x 120
+    with the wall)."""
     sc = base_params(
         name="film_flux_r%g_%dx%d+%d" % (ratio, nx, ny, wall), nx=nx, ny=ny, heater_rows=wall, n_sub=n_sub,
         top_bc="const_pressure", bottom_tbc="flux", top_tbc="zero_grad", q_bottom=q,
-        rho_w=RHO_L, cv_w=CV, lambda_w=ratio * RHO_L * CV * K_DIFF, Gw0=0.0,
+        rho_w=3.0 * RHO_L, cv_w=CV, lambda_w=ratio * RHO_L * CV * K_DIFF, Gw0=0.0,
         flags=("diff_isotropic",) if isotropic else (),
         rho0=layered_density(nx, ny, film), T0=np.full((wall + ny, nx), T_SAT), precision=precision)
     return sc

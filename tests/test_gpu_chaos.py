@@ -1,7 +1,11 @@
 """Once pool boiling is under way, FP32 runs leave the FP64 trajectory pointwise; the
 comparable result is then the time-averaged wall heat flux (Sec. 4.4), which the FP32
-path must reproduce within 2 % of the FP64 oracle.  The FP64 path still tracks the
-oracle to round-off over the same runs."""
+path must reproduce within 2 % of the FP64 oracle.  The test shows all three parts of
+that statement on one chaotic run: the FP32 state has decorrelated from the oracle's by
+the start of the averaging window, its time-averaged flux is within 2 % of the
+oracle's, and 2 % lies above the spread of time averages between FP64 trajectories of
+the same configuration that differ only by an initial perturbation (the noise floor of
+the criterion).  The FP64 GPU path tracks the oracle pointwise over the whole run."""
 import numpy as np
 import pytest
 
@@ -9,32 +13,83 @@ from parity import log
 
 pytestmark = pytest.mark.gpu
 
+# 256 x 256 pool filled with liquid above a 25-row heater, sites every 32 columns, wall
+# superheat 0.15 Tc (Ja = 0.17), g = 3e-5: nucleate boiling with bubbles leaving
+# through the outlet.  FP32 and FP64 states are O(0.1) apart from about step 16000.
+N0, N1 = 16000, 36000  # averaging window [N0, N1)
 
-@pytest.mark.parametrize("superheat", [0.12, 0.20, 0.26])
-def test_time_averaged_wall_heat_flux_in_boiling(superheat):
-    from oracle.lbm import OracleSim
-    from paper_1812_10375_amd import surrogate as SG
+
+def _case(prec, perturb=0.0, seed=0):
+    from paper_1812_10375_amd import scenarios as S
+    sc = S.pool_boiling(nx=256, ny=256, heater_rows=25, superheat=0.15, g=3e-5, site_spacing=32,
+                        liquid_fraction=1.0, seed=0, precision=prec)
+    if perturb:
+        rng = np.random.default_rng(seed)
+        sc["rho0"] = sc["rho0"] * (1.0 + perturb * rng.uniform(-1.0, 1.0, sc["rho0"].shape))
+    return sc
+
+
+def _run_gpu(sc):
     from paper_1812_10375_amd.lbm import Lattice
-    proto = SG.Protocol(steps=6000, window=3000)
-    p = np.array([superheat, 32, 0.5, 3e-5])
-    q, rho = {}, {}
-    for kind in ("f32", "f64", "oracle"):
-        sc = proto.case(p, precision="f32" if kind == "f32" else "f64")
-        sim = OracleSim(sc) if kind == "oracle" else Lattice(sc)
-        sim.step(proto.steps - proto.window)
-        a = sim.observe()
-        sim.step(proto.window)
-        b = sim.observe()
-        assert b.get("status", 0) == 0 and b["error_flags"] == 0
-        q[kind] = SG.window_stats(a, b)
-        rho[kind] = sim.field("rho") if kind == "oracle" else sim.read("rho")
-    d32 = abs(q["f32"][0] / q["oracle"][0] - 1)
-    d64 = abs(q["f64"][0] / q["oracle"][0] - 1)
-    drift = np.abs(rho["f32"] - rho["oracle"]).max() / 6.5
-    log("[chaos] superheat %.2f: q oracle %.5e, FP32 rel diff %.2e, FP64 rel diff %.2e; FP32 pointwise "
-        "max|drho|/rho_l %.2e" % (superheat, q["oracle"][0], d32, d64, drift))
-    assert d32 <= 0.02
-    assert d64 <= 1e-10
+    lat = Lattice(sc)
+    lat.step(N0)
+    o0 = lat.observe()
+    r0 = lat.read("rho")
+    lat.step(N1 - N0)
+    o1 = lat.observe()
+    r1 = lat.read("rho")
+    lat.close()
+    return o0, o1, r0, r1
+
+
+def test_time_averaged_wall_heat_flux_once_boiling_is_chaotic():
+    from oracle.lbm import OracleSim
+    from paper_1812_10375_amd.surrogate import window_stats
+    log("[chaos] oracle: 256 x 256 + 25, %d steps" % N1)
+    orc = OracleSim(_case("f64"))
+    assert orc.step(N0) == 0
+    oo0, ro0 = orc.observe(), orc.field("rho")
+    assert orc.step(N1 - N0) == 0
+    oo1, ro1 = orc.observe(), orc.field("rho")
+    q_orc = window_stats(oo0, oo1)[0]
+
+    def rel(o0, o1):
+        return window_stats(o0, o1)[0] / q_orc - 1.0
+
+    # FP32: decorrelated from the oracle at the window start, within 2 % on the average
+    g0, g1, r0, r1 = _run_gpu(_case("f32"))
+    drift0 = np.abs(r0 - ro0).max() / 6.5
+    drift1 = np.abs(r1 - ro1).max() / 6.5
+    d32 = rel(g0, g1)
+    # FP64 on the GPU: the oracle's trajectory, pointwise
+    h0, h1, s0, s1 = _run_gpu(_case("f64"))
+    track = max(np.abs(s0 - ro0).max(), np.abs(s1 - ro1).max()) / 6.5
+    d64 = rel(h0, h1)
+    # the criterion's noise floor: FP64 trajectories of the same configuration whose
+    # initial densities differ by 1e-12 stay together (the deterministic floor); with a
+    # 1e-3 difference (damped as sound before nucleation, but enough to shift it) they
+    # decorrelate as the FP32 run does, and the spread of their time averages is the
+    # statistical floor
+    p0, p1, _, _ = _run_gpu(_case("f64", 1e-12, seed=1))
+    floor_det = abs(rel(p0, p1))
+    floor_stat, apart = 0.0, []
+    for seed in (1, 2, 3):
+        a0, a1, ra, _ = _run_gpu(_case("f64", 1e-3, seed=seed))
+        assert a1["status"] == 0 and a1["error_flags"] == 0
+        floor_stat = max(floor_stat, abs(rel(a0, a1)))
+        apart.append(np.abs(ra - ro0).max() / 6.5)
+    log("[chaos] q_bar oracle %.6e; FP32 %+.3e (max|drho|/rho_l %.2f at step %d, %.2f at %d); FP64 GPU %+.1e "
+        "(tracks the oracle to %.1e); floor: 1e-12 perturbation %.1e, decorrelated FP64 runs %.3e (apart by %s "
+        "at step %d)" % (q_orc, d32, drift0, N0, drift1, N1, d64, track, floor_det, floor_stat,
+                         ", ".join("%.2f" % a for a in apart), N0))
+    for o in (g1, h1, p1):
+        assert o["status"] == 0 and o["error_flags"] == 0
+    assert drift0 >= 0.05 and drift1 >= 0.05, "the FP32 run has not decorrelated"
+    assert abs(d32) <= 0.02
+    assert track <= 1e-8 and abs(d64) <= 1e-8
+    assert floor_det <= 1e-8
+    assert max(apart) >= 0.01, "no floor run decorrelated"
+    assert floor_stat < 0.02  # the 2 % criterion lies above the statistical noise floor
 
 
 def test_full_length_pool_boiling_run():

@@ -1,8 +1,18 @@
-"""Film evaporation driven by a wall heat flux (Sec. 3.3, scaled to a 10-row wall and a
-20-row film so that it settles in 60k steps).  With the finite-volume faces of Eq. 25
-the evaporated mass flux approaches q / h_fg whatever the wall-to-liquid conductivity
-ratio; with the isotropic comparison scheme (Eq. 20-21) it overshoots at ratio 3 and
-the run turns non-finite at ratio 10."""
+"""Film evaporation driven by a wall heat flux, at the size of Sec. 3.3: 20 columns, a
+20-row wall (rho_w = 3 rho_l, c_v,w = c_v) under a 50-row liquid film and 50 rows of
+vapour, q = 2e-4 through the bottom, a constant-pressure top, FP64, conductivity ratios
+lambda_w / lambda_l = 1, 3 and 10.  Over steps 350k-450k (the plateau of the evaporation
+rate, before the thinning film lowers it):
+
+* the finite-volume faces of Eq. 25 give the same evaporated mass flux m'' for every
+  ratio, and the heat flux is continuous across the wall-liquid face (Fig. 5);
+* the isotropic comparison scheme (Eq. 20-21) agrees at ratio 1, overshoots at ratio 3
+  with a jump of the heat flux at the face, and turns non-finite at ratio 10.
+
+m'' stays about 5% below the q / h_fg of Eq. 29 on this plateau: part of the wall's
+heat goes into the film and vapour as sensible heat, and the wall and film are still
+releasing stored heat as the film thins (the flux entering the fluid is 1.04 q).  The
+test asserts the measured band and reports the values."""
 import numpy as np
 import pytest
 
@@ -13,38 +23,88 @@ from parity import log
 pytestmark = pytest.mark.gpu
 
 Q = 2e-4
-STEPS, CHUNK = 60000, 5000
+HIST = 256
+W0, W1 = 350208, 450048  # window of whole history periods around 350k-450k steps
 
 
-def _mass_flux_ratio(ratios, isotropic):
+def _run(ratios, isotropic, targets=(W0, W1)):
+    """Batched paper-size runs replayed from a captured history period; observations at
+    the target steps (stopping at the first non-finite state)."""
+    import torch
     from paper_1812_10375_amd.lbm import BatchLattice
-    scs = [S.film_evaporation_flux(r, Q, nx=20, ny=50, film=20, wall=10, precision="f32", isotropic=isotropic)
-           for r in ratios]
+    scs = [S.film_evaporation_flux(r, Q, precision="f64", isotropic=isotropic) for r in ratios]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    bat = BatchLattice(scs, stream=s)
+    bat.observe()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bat.step(HIST)
+    obs, step = [], 0
+    for target in targets:
+        with torch.cuda.stream(s):
+            for _ in range((target - step) // HIST):
+                g.replay()
+        step = target
+        o = bat.observe(check=False)
+        obs.append(o)
+        if any(x["error_flags"] for x in o):
+            break
+    return bat, scs, obs
+
+
+def _face_fluxes(bat, i, sc):
+    """Heat flux through the horizontal faces around the wall-liquid face (face 0 joins
+    the top wall row and the first fluid row), x-averaged, in units of q."""
+    T, rho, nh = bat.read(i, "T"), bat.read(i, "rho"), sc["heater_rows"]
+    lam = np.vstack([np.full((nh, sc["nx"]), sc["lambda_w"]), rho * sc["cv"] * sc["k"]])
+    out = {}
+    for j in range(nh - 4, nh + 3):
+        lf = 2 * lam[j] * lam[j + 1] / (lam[j] + lam[j + 1])
+        out[j - nh + 1] = float((lf * (T[j] - T[j + 1])).mean() / Q)
+    return out
+
+
+def _mass_flux(o0, o1):
     h_fg = eos.latent_heat(S.T_SAT, S.OMEGA)
-    bat = BatchLattice(scs)
-    prev = bat.observe()
-    for _ in range(STEPS // CHUNK):
-        bat.step(CHUNK)
-        obs = bat.observe(check=False)
-        if any(o["error_flags"] for o in obs):
-            return None, obs
-        last = [-(o["mass"] - p["mass"]) / (CHUNK * 20) / (Q / h_fg) for o, p in zip(obs, prev)]
-        prev = obs
-    return np.array(last), obs
+    return np.array([-(b["mass"] - a["mass"]) / ((b["step"] - a["step"]) * 20) / (Q / h_fg)
+                     for a, b in zip(o0, o1)])
 
 
-def test_finite_volume_mass_flux_is_q_over_hfg_for_any_conductivity_ratio():
-    m, _ = _mass_flux_ratio((1, 3, 10), isotropic=False)
+@pytest.fixture(scope="module")
+def fv_runs():
+    bat, scs, (o0, o1) = _run((1, 3, 10), isotropic=False)
+    out = (_mass_flux(o0, o1), [_face_fluxes(bat, i, sc) for i, sc in enumerate(scs)], o1)
+    bat.close()
+    return out
+
+
+def test_finite_volume_mass_flux_and_face_flux_for_any_conductivity_ratio(fv_runs):
+    m, faces, o1 = fv_runs
     log("[film] FV m''/(q/h_fg) for ratios 1, 3, 10: %s" % np.round(m, 4))
-    assert np.all((m > 0.9) & (m < 1.05))
-    assert m.max() - m.min() < 0.02
+    for r, f in zip((1, 3, 10), faces):
+        log("[film] FV ratio %d face fluxes / q: %s" % (r, {k: round(v, 4) for k, v in f.items()}))
+    assert all(o["error_flags"] == 0 for o in o1)
+    assert m.max() - m.min() < 0.005           # independent of the conductivity ratio
+    assert np.all((m > 0.93) & (m < 1.0))      # measured 0.948
+    for f in faces:
+        # no jump across the wall-liquid face: the face flux changes there as between
+        # any two neighbouring faces (the slow release of stored heat)
+        steps = np.diff([f[k] for k in sorted(f)])
+        assert abs(f[0] - f[-1]) <= 2 * np.abs(steps).max() and np.abs(steps).max() < 0.005
 
 
-def test_isotropic_scheme_overshoots_and_fails_at_high_ratio():
-    fv, _ = _mass_flux_ratio((1,), isotropic=False)
-    m, _ = _mass_flux_ratio((1, 3), isotropic=True)
-    log("[film] isotropic m''/(q/h_fg) for ratios 1, 3: %s" % np.round(m, 4))
-    assert abs(m[0] - fv[0]) < 0.02
-    assert m[1] > 1.2
-    bad, obs = _mass_flux_ratio((10,), isotropic=True)
-    assert bad is None and obs[0]["error_flags"] != 0
+def test_isotropic_scheme_overshoots_jumps_and_fails_at_high_ratio(fv_runs):
+    m_fv = fv_runs[0][0]
+    bat, scs, (o0, o1) = _run((1, 3), isotropic=True)
+    m = _mass_flux(o0, o1)
+    jump = _face_fluxes(bat, 1, scs[1])
+    log("[film] isotropic m''/(q/h_fg) for ratios 1, 3: %s (FV %.4f); ratio 3 face fluxes / q: %s"
+        % (np.round(m, 4), m_fv, {k: round(v, 3) for k, v in jump.items()}))
+    assert abs(m[0] - m_fv) < 0.02
+    assert m[1] > 1.3
+    assert abs(jump[1] - jump[-1]) > 0.3       # the flux jumps across the wall-liquid face
+    bat.close()
+    bad, _, obs = _run((10,), isotropic=True, targets=(120 * HIST,))
+    assert any(o["error_flags"] for o in obs[-1])
+    bad.close()
