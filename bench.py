@@ -124,16 +124,17 @@ def recorded_traffic(kernel):
     return None
 
 
-def batched(steps=200, warmup=20):
+def batched(steps=200, warmup=20, full_steps=50000):
     """Throughput of the batched step on the 48-domain pool-boiling workload (uneven
-    sizes and superheats), with the energy tile height picked by the autotuner."""
+    sizes and superheats), with the energy tile heights picked by the autotuner: one
+    height for all domains, then one per size class."""
     import torch
     from paper_1812_10375_amd import scenarios as S
-    from paper_1812_10375_amd.lbm import BatchLattice, autotune_tile_rows
+    from paper_1812_10375_amd.lbm import BatchLattice, autotune, autotune_tile_rows
     scs = S.batched_pool_boiling()
-    rows, tuned_ms = autotune_tile_rows(scs, steps=10)
-    for sc in scs:
-        sc["tile_rows"] = rows
+    rows, uniform_ms = autotune_tile_rows(scs, steps=20)
+    scs, tuned_ms = autotune(scs, steps=20)
+    by_class = {"%dx%d" % (sc["nx"], sc["ny"]): sc["tile_rows"] for sc in scs}
     bat = BatchLattice(scs)
     bat.step(warmup)
     torch.cuda.synchronize()
@@ -147,8 +148,9 @@ def batched(steps=200, warmup=20):
     nodes = sum(sc["nx"] * sc["ny"] for sc in scs)
     out = {"workload": "batched_pool_boiling_48", "domains": len(scs), "nodes": nodes,
            "steps": steps, "ms_per_step": ms / steps,
-           "MLUPS": nodes * steps / (ms * 1e-3) / 1e6, "tile_rows": rows,
-           "autotune_ms_per_step": tuned_ms, "status": max(abs(o["status"]) for o in obs)}
+           "MLUPS": nodes * steps / (ms * 1e-3) / 1e6, "tile_rows": by_class,
+           "autotune_ms_per_step": tuned_ms, "uniform_tile_rows": rows,
+           "uniform_autotune_ms_per_step": uniform_ms, "status": max(abs(o["status"]) for o in obs)}
     bat.close()
     # the same steps captured once in a HIP graph (one diagnostics-history period) and
     # replayed: the first replay warms up, the second is timed
@@ -172,6 +174,32 @@ def batched(steps=200, warmup=20):
     obs = bat.observe(check=False)
     out["graph"] = {"steps": hist, "ms_per_step": gms / hist, "MLUPS": nodes * hist / (gms * 1e-3) / 1e6,
                     "status": max(abs(o["status"]) for o in obs)}
+    if full_steps:
+        # the workload at its stated length, replaying the captured period: the first half
+        # settles, the second half is the averaging window of each domain's wall flux
+        from paper_1812_10375_amd.surrogate import window_stats
+        reps = -(-full_steps // hist)
+        half = reps // 2
+        e0.record(s)
+        with torch.cuda.stream(s):
+            for _ in range(half - 2):
+                g.replay()
+        w0 = bat.observe(check=False)
+        with torch.cuda.stream(s):
+            for _ in range(reps - half):
+                g.replay()
+        e1.record(s)
+        torch.cuda.synchronize()
+        fms = e0.elapsed_time(e1)
+        w1 = bat.observe(check=False)
+        q = [window_stats(a, b)[0] for a, b in zip(w0, w1)]
+        out["full_length"] = {"steps": w1[0]["step"], "window": [w0[0]["step"], w1[0]["step"]],
+                              "ms_per_step": fms / ((reps - 2) * hist),
+                              "MLUPS": nodes * (reps - 2) * hist / (fms * 1e-3) / 1e6,
+                              "status": max(abs(o["status"]) for o in w1),
+                              "q_bottom_mean_window": q,
+                              "superheat_Tc": [round((sc["T_bottom"] - S.T_SAT) / S.TC, 4) for sc in scs],
+                              "size": ["%dx%d" % (sc["nx"], sc["ny"]) for sc in scs]}
     bat.close()
     return out
 
@@ -294,6 +322,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-domain measurement")
     ap.add_argument("--no-boiling-curve", action="store_true",
                     help="skip the boiling-curve points/hour comparison (plain vs batched + surrogate)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the launch-shape autotuner on the headline domain (its trial launches "
+                         "run the same kernels at other tile shapes)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes five times "
@@ -360,6 +391,13 @@ def main():
     ob = lat.observe(check=False)
     nodes = sc["nx"] * sc["ny"]
     two = two_launch_reference(sc, args.steps, args.warmup)
+    # what the launch-shape autotuner picks for this domain (tile height and launch mode)
+    tuned = None
+    if not args.no_autotune:
+        from paper_1812_10375_amd.lbm import autotune
+        (tsc,), tms = autotune([sc], steps=100)
+        tuned = {"tile_rows": tsc["tile_rows"], "launch": "one" if "one_launch" in tsc["flags"] else "two",
+                 "ms_per_step": tms}
     mlups = nodes * args.steps / (ms * 1e-3) / 1e6
 
     per = {k: (v[0] / v[1] if v[1] else float("nan")) for k, v in kt.items()}
@@ -419,6 +457,7 @@ def main():
                       "step_frac_median": step_bytes / (sus[2] * 1e-3) / 1e9 / HBM_PEAK_GBPS},
         "status": ob["status"],
         "two_launches": two,
+        "autotuned": tuned,
     }
     lat.close()
     if not args.no_hbm_resident:

@@ -95,9 +95,13 @@ enum {
  *   Gw0, Gw_top           wall strengths of Eq. 10 at the bottom wall and a top wall
  *   n_sites, site_*       nucleation sites (Sec. 4.2): centre x, width, minimum strength;
  *                         host arrays of n_sites doubles (may be NULL when n_sites = 0)
- *   tile_rows             rows of temperature grid per energy tile (a performance knob: the
- *                         fields do not depend on it, the FP64 sums behind the diagnostics
- *                         do, in their last bits); 0 = automatic (one domain: tiles that fill
+ *   tile_rows             rows of temperature grid per energy tile, a performance knob.  In
+ *                         FP64 and under LBM_DIFF_ISOTROPIC the fields do not depend on it.
+ *                         The FP32 finite-volume path evaluates tiles whose rows are all
+ *                         away from the boundaries in an all-fluid form of the same
+ *                         coefficients (other rounding), so its fields follow the tile
+ *                         shape in their last bits; so do the FP64 sums behind the
+ *                         diagnostics, at any precision.  0 = automatic (one domain: tiles that fill
  *                         the device in one round; a batch: the tallest tiles), otherwise
  *                         clamped to [8, 48].  It sets the number of tile rows; the FP32
  *                         path (without LBM_DIFF_ISOTROPIC) then shortens the first and the
@@ -269,6 +273,24 @@ int lbm_batch_destroy(lbm_batch *b);
 int lbm_autotune_tile_rows(const lbm_config *cfgs, int n, void *d_workspace, size_t ws_bytes,
                            void *hip_stream, const double *const *rho0_host,
                            const double *const *T0_host, int steps, int *best_rows, double *best_ms);
+
+/*
+ * Launch-shape autotuner, a superset of lbm_autotune_tile_rows (same workspace, inputs,
+ * timing, caching and synchronisation).
+ *   n >= 2: it times every candidate energy tile height for all domains together, then,
+ *           taking the size classes (nx, ny, heater_rows) in order of their node count,
+ *           every candidate height for one class with the others held at their best.
+ *   n = 1:  it times the domain on its own path (lbm_init / lbm_step) at the automatic
+ *           height (tile_rows = 0) and every candidate height; an FP32 domain with n_sub = 1 and the finite-volume faces is timed
+ *           both as two launches per step and as the fused one-launch step.
+ * rows[i] (n entries) receives domain i's tile_rows and flags[i] cfgs[i].flags with the
+ * chosen launch mode (LBM_ONE_LAUNCH or LBM_TWO_LAUNCHES for a domain timed both ways,
+ * neither otherwise); pass both back in the configurations.  *best_ms is the time per
+ * step of that choice.  The choice changes results only as tile_rows does (above).
+ */
+int lbm_autotune(const lbm_config *cfgs, int n, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                 const double *const *rho0_host, const double *const *T0_host, int steps,
+                 int32_t *rows, uint32_t *flags, double *best_ms);
 
 /* Static description of a status code. */
 const char *lbm_strerror(int status);

@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "lbm_api.h"
@@ -662,6 +663,108 @@ lbm_config batch_member(const lbm_config& c) {
   return m;
 }
 
+// Candidate energy tile heights of the autotuners.
+std::vector<int> tile_candidates(const lbm_config& c) {
+  const int hmax = c.precision == LBM_F64 ? E_HMAX : E_HMAX_F32;
+  return {8, 12, 16, 20, 24, 32, 40, hmax};
+}
+
+// Autotuner cache key: what the timing depends on besides the tile shape.
+std::string tune_key(const lbm_config* cfgs, int n) {
+  std::string key = std::to_string(cfgs[0].precision) + "/" + std::to_string(cfgs[0].n_sub) + "/" +
+                    std::to_string(cfgs[0].flags & LBM_DIFF_ISOTROPIC);
+  for (int i = 0; i < n; ++i)
+    key += "/" + std::to_string(cfgs[i].nx) + "x" + std::to_string(cfgs[i].ny) + "+" +
+           std::to_string(cfgs[i].heater_rows);
+  return key;
+}
+
+struct TuneEntry {
+  std::vector<int> rows;
+  std::vector<uint32_t> flags;
+  double ms;
+};
+std::mutex tune_mu;
+std::map<std::string, TuneEntry> tune_cache;
+
+bool tune_cached(const std::string& key, int* rows, uint32_t* flags, double* ms, int n) {
+  std::lock_guard<std::mutex> lk(tune_mu);
+  auto it = tune_cache.find(key);
+  if (it == tune_cache.end()) return false;
+  for (int i = 0; i < n; ++i) {
+    rows[i] = it->second.rows[i];
+    if (flags) flags[i] = it->second.flags[i];
+  }
+  *ms = it->second.ms;
+  return true;
+}
+
+void tune_store(const std::string& key, const int* rows, const uint32_t* flags, double ms, int n) {
+  std::lock_guard<std::mutex> lk(tune_mu);
+  tune_cache[key] = TuneEntry{std::vector<int>(rows, rows + n), std::vector<uint32_t>(flags, flags + n), ms};
+}
+
+// Times `steps` steps, after `steps` warm-up steps, of a batch or of one domain built in
+// the caller's workspace; rc keeps the first error.
+struct Timer {
+  void* ws;
+  size_t bytes;
+  void* stream;
+  const double* const* rho0;
+  const double* const* T0;
+  int steps;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = LBM_OK;
+  Timer(void* w, size_t b, void* s, const double* const* r, const double* const* t, int n)
+      : ws(w), bytes(b), stream(s), rho0(r), T0(t), steps(n) {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = LBM_EHIP;
+  }
+  ~Timer() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+  template <typename Step>
+  double time(Step&& step) {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    float ms = 0.f;
+    int r = step();
+    if (!r && (hipEventRecord(e0, st) != hipSuccess || (r = step()) != 0 || hipEventRecord(e1, st) != hipSuccess ||
+               hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      r = r ? r : LBM_EHIP;
+    if (r && !rc) rc = r;
+    return (double)ms / steps;
+  }
+  double batch(const std::vector<lbm_config>& cs) {
+    if (rc) return 0.0;
+    lbm_batch* b = nullptr;
+    const int r = lbm_batch_init(cs.data(), (int)cs.size(), ws, bytes, stream, rho0, T0, &b);
+    if (r) {
+      rc = r;
+      return 0.0;
+    }
+    const double per = time([&] { return lbm_batch_step(b, steps); });
+    lbm_batch_destroy(b);
+    return per;
+  }
+  double single(const lbm_config& c) {
+    if (rc) return 0.0;
+    lbm_ctx* h = nullptr;
+    const int r = lbm_init(&c, ws, bytes, stream, rho0[0], T0[0], &h);
+    if (r) {
+      rc = r;
+      return 0.0;
+    }
+    const double per = time([&] { return lbm_step(h, steps); });
+    if (!rc) {
+      // a step failure surfaces only at synchronisation
+      const int st = hip_ok(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+      if (st) rc = st;
+    }
+    lbm_destroy(h);
+    return per;
+  }
+};
+
 }  // namespace
 
 extern "C" {
@@ -783,64 +886,120 @@ int lbm_batch_destroy(lbm_batch* b) {
 int lbm_autotune_tile_rows(const lbm_config* cfgs, int n, void* d_workspace, size_t ws_bytes, void* hip_stream,
                            const double* const* rho0_host, const double* const* T0_host, int steps,
                            int* best_rows, double* best_ms) {
-  static std::mutex mu;
-  static std::map<std::string, std::pair<int, double>> cache;
   if (!best_rows || !best_ms || steps < 1 || !batch_compatible(cfgs, n)) return LBM_EINVAL;
   if (ws_bytes < lbm_batch_workspace_bytes(cfgs, n)) return LBM_ENOMEM;
-  std::string key = std::to_string(cfgs[0].precision) + "/" + std::to_string(cfgs[0].n_sub) + "/" +
-                    std::to_string(cfgs[0].flags & LBM_DIFF_ISOTROPIC);
-  for (int i = 0; i < n; ++i)
-    key += "/" + std::to_string(cfgs[i].nx) + "x" + std::to_string(cfgs[i].ny) + "+" +
-           std::to_string(cfgs[i].heater_rows);
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-      *best_rows = it->second.first;
-      *best_ms = it->second.second;
-      return LBM_OK;
-    }
-  }
-  const int hmax = cfgs[0].precision == LBM_F64 ? E_HMAX : E_HMAX_F32;
-  const int cand[] = {8, 12, 16, 20, 24, 32, 40, hmax};
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return LBM_EHIP;
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return LBM_EHIP;
-  }
+  const std::string key = "rows/" + tune_key(cfgs, n);
+  if (tune_cached(key, best_rows, nullptr, best_ms, 1)) return LBM_OK;
+  Timer t(d_workspace, ws_bytes, hip_stream, rho0_host, T0_host, steps);
+  if (t.rc) return t.rc;
   std::vector<lbm_config> cs(cfgs, cfgs + n);
   int best = 0;
   double bms = 0.0;
-  int rc = LBM_OK;
-  for (int r : cand) {
+  for (int r : tile_candidates(cfgs[0])) {
     for (auto& c : cs) c.tile_rows = r;
-    lbm_batch* b = nullptr;
-    rc = lbm_batch_init(cs.data(), n, d_workspace, ws_bytes, hip_stream, rho0_host, T0_host, &b);
-    if (rc) break;
-    float ms = 0.f;
-    rc = lbm_batch_step(b, steps);
-    if (!rc && (hipEventRecord(e0, st) != hipSuccess || (rc = lbm_batch_step(b, steps)) != 0 ||
-                hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-      rc = rc ? rc : LBM_EHIP;
-    lbm_batch_destroy(b);
-    if (rc) break;
-    const double per = (double)ms / steps;
+    const double per = t.batch(cs);
+    if (t.rc) return t.rc;
     if (best == 0 || per < bms) {
       best = r;
       bms = per;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (rc) return rc;
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    cache[key] = {best, bms};
-  }
+  const uint32_t fl = cfgs[0].flags;
+  tune_store(key, &best, &fl, bms, 1);
   *best_rows = best;
+  *best_ms = bms;
+  return LBM_OK;
+}
+
+int lbm_autotune(const lbm_config* cfgs, int n, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                 const double* const* rho0_host, const double* const* T0_host, int steps, int32_t* rows,
+                 uint32_t* flags, double* best_ms) {
+  if (!rows || !flags || !best_ms || steps < 1 || !batch_compatible(cfgs, n)) return LBM_EINVAL;
+  if (ws_bytes < lbm_batch_workspace_bytes(cfgs, n)) return LBM_ENOMEM;
+  const std::string key = "shape/" + tune_key(cfgs, n);
+  int cr[1024];
+  uint32_t cf[1024];
+  if (n <= 1024 && tune_cached(key, cr, cf, best_ms, n)) {
+    for (int i = 0; i < n; ++i) {
+      rows[i] = cr[i];
+      flags[i] = cf[i];
+    }
+    return LBM_OK;
+  }
+  Timer t(d_workspace, ws_bytes, hip_stream, rho0_host, T0_host, steps);
+  if (t.rc) return t.rc;
+  const std::vector<int> cand = tile_candidates(cfgs[0]);
+  std::vector<lbm_config> cs(cfgs, cfgs + n);
+  for (auto& c : cs) c.flags &= ~(LBM_ONE_LAUNCH | LBM_TWO_LAUNCHES);
+  double bms = 0.0;
+  if (n == 1) {
+    // one domain: its own path (lbm_init / lbm_step), both launch modes where both apply
+    const lbm_config& c0 = cfgs[0];
+    const bool both = c0.precision == LBM_F32 && c0.n_sub == 1 && !(c0.flags & LBM_DIFF_ISOTROPIC);
+    lbm_config best = cs[0];
+    std::vector<int> cand1 = {0};  // the automatic height first (tiles that fill the device)
+    cand1.insert(cand1.end(), cand.begin(), cand.end());
+    for (uint32_t mode : {LBM_TWO_LAUNCHES, LBM_ONE_LAUNCH}) {
+      if (!both && mode == LBM_ONE_LAUNCH) continue;
+      for (int r : cand1) {
+        lbm_config c = cs[0];
+        c.tile_rows = r;
+        if (both) c.flags |= mode;
+        const double per = t.single(c);
+        if (t.rc) return t.rc;
+        if (bms == 0.0 || per < bms) {
+          bms = per;
+          best = c;
+        }
+      }
+    }
+    cs[0] = best;
+  } else {
+    // a batch: one height for all domains, then each size class on its own, the class
+    // with the most nodes first, the other classes held at their best heights
+    int r0 = 0;
+    for (int r : cand) {
+      for (auto& c : cs) c.tile_rows = r;
+      const double per = t.batch(cs);
+      if (t.rc) return t.rc;
+      if (r0 == 0 || per < bms) {
+        r0 = r;
+        bms = per;
+      }
+    }
+    for (auto& c : cs) c.tile_rows = r0;
+    std::map<std::tuple<int, int, int>, long long> nodes;
+    for (const auto& c : cs) nodes[{c.nx, c.ny, c.heater_rows}] += (long long)c.nx * (c.ny + c.heater_rows);
+    std::vector<std::pair<long long, std::tuple<int, int, int>>> order;
+    for (const auto& kv : nodes) order.push_back({kv.second, kv.first});
+    std::stable_sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    if (order.size() > 1) {
+      for (const auto& cls : order) {
+        int cur = r0;
+        for (const auto& c : cs)
+          if (std::make_tuple(c.nx, c.ny, c.heater_rows) == cls.second) cur = c.tile_rows;
+        for (int r : cand) {
+          if (r == cur) continue;
+          std::vector<lbm_config> trial = cs;
+          for (auto& c : trial)
+            if (std::make_tuple(c.nx, c.ny, c.heater_rows) == cls.second) c.tile_rows = r;
+          const double per = t.batch(trial);
+          if (t.rc) return t.rc;
+          if (per < bms) {
+            bms = per;
+            cs = trial;
+          }
+        }
+      }
+    }
+  }
+  std::vector<int> rr(n);
+  std::vector<uint32_t> ff(n);
+  for (int i = 0; i < n; ++i) {
+    rr[i] = rows[i] = cs[i].tile_rows;
+    ff[i] = flags[i] = cs[i].flags;
+  }
+  if (n <= 1024) tune_store(key, rr.data(), ff.data(), bms, n);
   *best_ms = bms;
   return LBM_OK;
 }

@@ -109,6 +109,9 @@ def library():
         L.lbm_autotune_tile_rows.restype = C.c_int
         L.lbm_autotune_tile_rows.argtypes = [cfgp, C.c_int, vp, C.c_size_t, vp, dpp, dpp, C.c_int,
                                              C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.lbm_autotune.restype = C.c_int
+        L.lbm_autotune.argtypes = [cfgp, C.c_int, vp, C.c_size_t, vp, dpp, dpp, C.c_int,
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_uint32), C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -406,3 +409,27 @@ def autotune_tile_rows(scs, steps=20, device=None, stream=None):
     if rc != 0:
         raise LbmError(rc, "lbm_autotune_tile_rows")
     return rows.value, ms.value
+
+
+def autotune(scs, steps=20, device=None, stream=None):
+    """Launch shape for these scenarios (a batch, or one domain on its own path), cached
+    per process by the library: returns (scenarios with the chosen tile_rows and launch
+    mode, ms per step)."""
+    import torch
+    inp = _BatchInputs(scs)
+    nbytes = inp.workspace_bytes()
+    if nbytes == 0:
+        raise LbmError(-1, "lbm_batch_workspace_bytes")
+    dev = torch.device("cuda") if device is None else torch.device(device)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream(dev) if stream is None else stream
+    rows, flags, ms = (C.c_int32 * inp.n)(), (C.c_uint32 * inp.n)(), C.c_double()
+    rc = library().lbm_autotune(inp.cfgs, inp.n, C.c_void_p(ws.data_ptr()), nbytes, C.c_void_p(st.cuda_stream),
+                                inp.rho0, inp.T0, int(steps), rows, flags, C.byref(ms))
+    if rc != 0:
+        raise LbmError(rc, "lbm_autotune")
+    out = []
+    for sc, r, f in zip(scs, rows, flags):
+        names = tuple(k for k, bit in FLAG_BITS.items() if f & bit)
+        out.append(dict(sc, tile_rows=int(r), flags=names))
+    return out, ms.value

@@ -130,3 +130,43 @@ def test_autotuner_picks_a_candidate_and_caches_it():
     assert rows in (8, 12, 16, 20, 24, 32, 40, 48)
     assert ms > 0
     assert autotune_tile_rows(scs, steps=5) == (rows, ms)
+
+
+def test_shape_autotuner_per_size_class_and_launch_mode():
+    # the batch tuner returns a candidate height per domain, one per size class; the
+    # one-domain tuner also picks the launch mode; runs with the tuned shapes agree with
+    # the default shapes to FP32 rounding (tiles away from the boundaries evaluate the
+    # coefficients in their all-fluid form, so the FP32 fields follow the tile shape in
+    # their last bits)
+    from paper_1812_10375_amd.lbm import BatchLattice, Lattice, autotune
+    scs = _mixed("f32", rows=0)
+    tuned, ms = autotune(scs, steps=5)
+    log("[batch] shape autotune rows=%s ms=%.4f" % ([sc["tile_rows"] for sc in tuned], ms))
+    assert ms > 0 and all(sc["tile_rows"] in (8, 12, 16, 20, 24, 32, 40, 48) for sc in tuned)
+    cls = {}
+    for sc in tuned:
+        assert cls.setdefault((sc["nx"], sc["ny"], sc["heater_rows"]), sc["tile_rows"]) == sc["tile_rows"]
+    again, ms2 = autotune(scs, steps=5)
+    assert ms2 == ms and [sc["tile_rows"] for sc in again] == [sc["tile_rows"] for sc in tuned]
+    ref, got = BatchLattice(scs), BatchLattice(tuned)
+    ref.step(40)
+    got.step(40)
+    for i in range(len(scs)):
+        for k in ("f", "T"):
+            a, b = ref.read(i, k), got.read(i, k)
+            assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max(), (i, k)
+    ref.close()
+    got.close()
+    one = S.pool_boiling(nx=256, ny=128, heater_rows=8, n_sites=2, min_spacing=32, seed=5, precision="f32")
+    (t1,), ms1 = autotune([one], steps=5)
+    log("[batch] one-domain autotune rows=%d flags=%s ms=%.4f" % (t1["tile_rows"], t1["flags"], ms1))
+    assert len({"one_launch", "two_launches"} & set(t1["flags"])) == 1
+    assert t1["tile_rows"] in (0, 8, 12, 16, 20, 24, 32, 40, 48)
+    a, b = Lattice(one), Lattice(t1)
+    a.step(40)
+    b.step(40)
+    for k in ("f", "T"):
+        x, y = a.read(k), b.read(k)
+        assert np.abs(x - y).max() <= 1e-5 * np.abs(x).max(), k
+    a.close()
+    b.close()
