@@ -116,6 +116,11 @@ __device__ __forceinline__ void stc(T* p, T v) {
   if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   else *p = v;
 }
+// stc at element i of a uniform base (32-bit offset, as ld32 / st32)
+template <bool COH, typename T>
+__device__ __forceinline__ void stc32(T* __restrict__ base, unsigned i, T v) {
+  stc<COH>(reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)), v);
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -205,34 +210,32 @@ template <typename real>
 __device__ __forceinline__ void pull(const real* __restrict__ fs, const real* __restrict__ topin,
                                      int gx, int y, int nx, int ny, size_t N, int top_bc,
                                      real f[9]) {
-  const int xm = wrap1(gx - 1, nx), xp = wrap1(gx + 1, nx);
-  const size_t row = (size_t)y * nx;
-  f[0] = fs[row + gx];
-  f[1] = fs[N + row + xm];
-  f[3] = fs[3 * N + row + xp];
-  if (y > 0) {
-    const size_t rb = row - nx;
-    f[2] = fs[2 * N + rb + gx];
-    f[5] = fs[5 * N + rb + xm];
-    f[6] = fs[6 * N + rb + xp];
+  // y is uniform across the wave, so every choice below is a choice of a uniform plane
+  // base and of a per-lane 32-bit offset (one load each, in the scalar-base form)
+  const unsigned xm = wrap1(gx - 1, nx), xp = wrap1(gx + 1, nx), x = gx;
+  const unsigned row = (unsigned)y * (unsigned)nx;
+  auto pl = [&](int i) { return fs + (size_t)i * N; };
+  f[0] = ld32(pl(0), row + x);
+  f[1] = ld32(pl(1), row + xm);
+  f[3] = ld32(pl(3), row + xp);
+  // below: the row under y, or bounce-back of this node's 4, 7, 8 at the bottom wall
+  const bool below = y > 0;
+  const unsigned rb = row - nx;
+  f[2] = ld32(pl(below ? 2 : 4), below ? rb + x : row + x);
+  f[5] = ld32(pl(below ? 5 : 7), below ? rb + xm : row + x);
+  f[6] = ld32(pl(below ? 6 : 8), below ? rb + xp : row + x);
+  // above: the row over y, bounce-back of 2, 5, 6 under a top wall, or the open top's
+  // incoming populations
+  if (y < ny - 1 || top_bc == TOP_WALL) {
+    const bool above = y < ny - 1;
+    const unsigned ra = row + nx;
+    f[4] = ld32(pl(above ? 4 : 2), above ? ra + x : row + x);
+    f[7] = ld32(pl(above ? 7 : 5), above ? ra + xp : row + x);
+    f[8] = ld32(pl(above ? 8 : 6), above ? ra + xm : row + x);
   } else {
-    f[2] = fs[4 * N + row + gx];
-    f[5] = fs[7 * N + row + gx];
-    f[6] = fs[8 * N + row + gx];
-  }
-  if (y < ny - 1) {
-    const size_t ra = row + nx;
-    f[4] = fs[4 * N + ra + gx];
-    f[7] = fs[7 * N + ra + xp];
-    f[8] = fs[8 * N + ra + xm];
-  } else if (top_bc == TOP_WALL) {
-    f[4] = fs[2 * N + row + gx];
-    f[7] = fs[5 * N + row + gx];
-    f[8] = fs[6 * N + row + gx];
-  } else {
-    f[4] = topin[gx];
-    f[7] = topin[nx + gx];
-    f[8] = topin[2 * nx + gx];
+    f[4] = ld32(topin, x);
+    f[7] = ld32(topin, nx + x);
+    f[8] = ld32(topin, 2 * nx + x);
   }
 }
 
@@ -596,7 +599,7 @@ __device__ __forceinline__ void collide_tile(
 #pragma unroll
       for (int i = 1; i < 9; ++i) r += f[k][i];
       rr[k] = r;
-      const double TE = (P.flags & FREEZE_EOS_T) ? P.T_sat : (double)Tcur[(size_t)(y + P.nh) * nx + gxo];
+      const double TE = (P.flags & FREEZE_EOS_T) ? P.T_sat : (double)ld32(Tcur, (unsigned)(y + P.nh) * (unsigned)nx + gxo);
       if constexpr (sizeof(real) == 8) ps = eos_psi_plain(P, r, TE, err);
       else ps = sqrtf((float)eos_psi2(P, (double)r, TE, err));
     }
@@ -618,7 +621,7 @@ __device__ __forceinline__ void collide_tile(
       real r = fr[0];
 #pragma unroll
       for (int i = 1; i < 9; ++i) r += fr[i];
-      const double TE = (P.flags & FREEZE_EOS_T) ? P.T_sat : (double)Tcur[(size_t)(y + P.nh) * nx + gx];
+      const double TE = (P.flags & FREEZE_EOS_T) ? P.T_sat : (double)ld32(Tcur, (unsigned)(y + P.nh) * (unsigned)nx + gx);
       unsigned e2 = 0;
       if constexpr (sizeof(real) == 8) ps = eos_psi_plain(P, r, TE, e2);
       else ps = sqrtf((float)eos_psi2(P, (double)r, TE, e2));
@@ -694,12 +697,12 @@ __device__ __forceinline__ void collide_tile(
       const real qsig = (fmx * fmx + fmy * fmy) * fast_rcp(pc2);
       collide(f[k], r, Fx, Fy, qsig, cc, ux, uy);
     }
-    const size_t n = (size_t)y * nx + gxo;
+    const unsigned n = (unsigned)y * (unsigned)nx + gxo;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) stc<COH>(fdst + i * N + n, f[k][i]);
-    stc<COH>(rho_out + n, r);
-    stc<COH>(ux_out + n, ux);
-    stc<COH>(uy_out + n, uy);
+    for (int i = 0; i < 9; ++i) stc32<COH>(fdst + i * N, n, f[k][i]);
+    stc32<COH>(rho_out, n, r);
+    stc32<COH>(ux_out, n, ux);
+    stc32<COH>(uy_out, n, uy);
     // post-collision mass (per node in the field precision, accumulated in FP64); the
     // open top's net exchange is added by the outlet block of the energy launch
     const real ms = ((f[k][0] + f[k][1]) + (f[k][2] + f[k][3])) + ((f[k][4] + f[k][5]) + (f[k][6] + f[k][7])) + f[k][8];
