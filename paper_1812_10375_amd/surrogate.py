@@ -9,7 +9,8 @@ the LB method for every point.  This module adds two faster forms:
 * batched runs: many points advance together in one batched step;
 * a surrogate: an ensemble of small MLPs trained on batched runs of the method, with
   BF16 matrix-core kernels.  A query falls back to batched plain runs where the
-  members disagree by more than a threshold.
+  members disagree by more than a threshold, or where the training runs nearest to it
+  were predicted worse than that when left out of a member's resample.
 
 Every step of the method runs in the library's kernels.  This module only builds
 scenarios, reads observations and moves arrays.
@@ -26,12 +27,27 @@ INPUTS = ("superheat", "site_spacing", "Gw0", "g")
 
 
 class Protocol:
-    """Run protocol of one point: a full liquid pool of nx x ny above a heater of
-    `heater_rows` rows, `steps` LB steps, statistics over the last `window` steps."""
+    """Run protocol of one point: a pool of nx x ny filled with liquid above a heater of
+    `heater_rows` rows, `steps` LB steps, statistics over the last `window` steps.
 
-    def __init__(self, nx=128, ny=96, heater_rows=8, steps=4000, window=2000):
+    The default is the smallest domain of the batched pool-boiling workload (256 x 256
+    above 25 heater rows) run for that workload's 50k steps, averaged over the whole run:
+    the heat a run draws through the heater's bottom per step, and its variance over the
+    steps.  At this size the later part of a run is still a transient (the pool keeps
+    warming: averages over steps 25k-50k and 25k-150k differ by 32% at the median), so a
+    late window is no steadier a boiling-curve value, while the whole-run average is
+    deterministic (runs from initial densities perturbed by 1e-3 agree to 0.1% at the
+    median) and varies smoothly enough with the inputs to be learnt."""
+
+    def __init__(self, nx=256, ny=256, heater_rows=25, steps=50000, window=50000):
+        if not 0 < window <= steps:
+            raise ValueError("the window must lie within the run")
         self.nx, self.ny, self.heater_rows = nx, ny, heater_rows
         self.steps, self.window = steps, window
+
+    def describe(self):
+        return "%dx%d+%d pool, all liquid, %d steps, statistics over the last %d" % (
+            self.nx, self.ny, self.heater_rows, self.steps, self.window)
 
     def case(self, p, precision="f32"):
         sc = S.pool_boiling(nx=self.nx, ny=self.ny, heater_rows=self.heater_rows, superheat=float(p[0]),
@@ -60,9 +76,9 @@ def window_stats(o0, o1):
     return mw, max(m2, 0.0) / nw
 
 
-def run_plain(points, proto, chunk=512):
+def run_plain(points, proto, chunk=512, progress=None):
     """Boiling-curve points by batched runs of the method: returns [n][2] (mean, var)
-    and the status of each run."""
+    and the status of each run.  progress(done, total) is called after every batch."""
     from .lbm import BatchLattice
     points = np.asarray(points, dtype=np.float64).reshape(-1, 4)
     out = np.zeros((len(points), 2))
@@ -81,13 +97,18 @@ def run_plain(points, proto, chunk=512):
             out[a + i] = window_stats(u, v)
             status[a + i] = v["error_flags"]
         bat.close()
+        if progress:
+            progress(a + len(part), len(points))
     return out, status
 
 
-def run_plain_single(point, proto):
-    """One boiling-curve point by a single-domain run (the plain per-run form)."""
+def run_plain_single(point, proto, tile_rows=0):
+    """One boiling-curve point by a single-domain run (the plain per-run form); tile_rows
+    as in the library's configuration (0: the automatic tiles of one domain)."""
     from .lbm import Lattice
-    lat = Lattice(proto.case(point))
+    sc = proto.case(point)
+    sc["tile_rows"] = tile_rows
+    lat = Lattice(sc)
     lat.step(proto.steps - proto.window)
     o0 = lat.observe()
     lat.step(proto.window)
@@ -99,11 +120,18 @@ def run_plain_single(point, proto):
 class Surrogate:
     """Ensemble of MLPs on the GPU mapping scaled inputs to the standardised logarithms
     of the heat-flux mean and variance (so that errors are relative).  Each member is
-    trained on its own bootstrap resample of the points; the members' spread of
-    log(mean) estimates the relative uncertainty of a prediction."""
+    trained on its own bootstrap resample of the points.  Two estimates of the relative
+    error of a prediction come with it:
 
-    def __init__(self, members=4, seed=1):
-        self.members, self.seed = members, seed
+    * the members' spread of log q (the model's uncertainty);
+    * the out-of-bag error of the nearest training runs: each training run is predicted
+      by the members whose resample left it out, and a query takes the mean of that
+      error over its `k_local` nearest runs in the scaled input space.  This catches
+      regions where the members agree but the flux varies faster than the runs resolve
+      (near the boiling crisis), which the spread alone misses."""
+
+    def __init__(self, members=4, seed=1, k_local=8):
+        self.members, self.seed, self.k_local = members, seed, k_local
         self.net = None
 
     @staticmethod
@@ -113,7 +141,8 @@ class Surrogate:
 
     def fit(self, points, values, steps=4000, lr=2e-3, lr_end=5e-5):
         """Train every member on a bootstrap resample of the points (full batch, Adam,
-        cosine-decayed rate); returns the final losses."""
+        cosine-decayed rate), then record every run's out-of-bag error; returns the final
+        losses."""
         import torch
         from .mlp import MLPEnsemble
         X = self.scale(points)
@@ -129,26 +158,47 @@ class Surrogate:
         for it in range(steps):
             r = lr_end + 0.5 * (lr - lr_end) * (1.0 + np.cos(np.pi * it / steps))
             self.net.train_step(Xd, Td, r)
-        return self.net.backward(Xd, Td).cpu().numpy()
+        losses = self.net.backward(Xd, Td).cpu().numpy()
+        # out-of-bag error of every training run (NaN where every member drew it)
+        oob = np.ones((self.members, len(X)), dtype=bool)
+        for m in range(self.members):
+            oob[m, idx[m]] = False
+        Lm = self._members(X)[:, :, 0]
+        n_oob = oob.sum(axis=0)
+        lo = np.where(oob, Lm, 0.0).sum(axis=0) / np.maximum(n_oob, 1)
+        err = np.abs(np.exp(lo - L[:, 0]) - 1.0)
+        self.X_train, self.oob_err = X, np.where(n_oob > 0, err, np.nan)
+        return losses
+
+    def _members(self, Xs):
+        """Every member's logarithms of (q mean, q variance) at scaled inputs: [members][n][2]."""
+        outs = []
+        for a in range(0, len(Xs), self.net.max_batch):
+            outs.append(self.net.forward(Xs[a:a + self.net.max_batch]).cpu().numpy().astype(np.float64))
+        return np.concatenate(outs, axis=1) * self.sd + self.mu
 
     def predict(self, points):
-        """Ensemble estimate of (q mean, q variance) and the members' spread of log q."""
+        """Ensemble estimate of (q mean, q variance), the members' spread of log q, and
+        the mean out-of-bag error of the nearest training runs."""
         Xq = self.scale(points)
-        outs = []
-        for a in range(0, len(Xq), self.net.max_batch):
-            outs.append(self.net.forward(Xq[a:a + self.net.max_batch]).cpu().numpy().astype(np.float64))
-        Y = np.concatenate(outs, axis=1) * self.sd + self.mu   # [members][n][2], logarithms
+        Y = self._members(Xq)
         vals = np.exp(Y.mean(axis=0))
-        return vals, Y[:, :, 0].std(axis=0)
+        local = np.empty(len(Xq))
+        for a in range(0, len(Xq), 2048):
+            d = np.linalg.norm(Xq[a:a + 2048, None, :] - self.X_train[None], axis=2)
+            near = np.argpartition(d, self.k_local - 1, axis=1)[:, :self.k_local]
+            local[a:a + 2048] = np.nanmean(self.oob_err[near], axis=1)
+        return vals, Y[:, :, 0].std(axis=0), local
 
 
-def boiling_curve(surrogate, points, proto, threshold=0.05):
-    """Boiling-curve values for `points`: the surrogate's prediction where the members'
-    spread of log q is within `threshold`, batched plain runs of the method elsewhere."""
-    vals, spread = surrogate.predict(points)
-    fall = np.nonzero(spread > threshold)[0]
+def boiling_curve(surrogate, points, proto, threshold=0.05, progress=None):
+    """Boiling-curve values for `points`: the surrogate's prediction where both error
+    estimates (the members' spread of log q, the out-of-bag error of the nearest runs)
+    are within `threshold`, batched plain runs of the method elsewhere."""
+    vals, spread, local = surrogate.predict(points)
+    fall = np.nonzero((spread > threshold) | (local > threshold))[0]
     if len(fall):
-        vals[fall], _ = run_plain(np.asarray(points)[fall], proto)
+        vals[fall], _ = run_plain(np.asarray(points)[fall], proto, progress=progress)
     return vals, fall
 
 
