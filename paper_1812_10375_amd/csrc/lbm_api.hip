@@ -499,6 +499,9 @@ int write_state(lbm_ctx* h, const void* src) {
                      h->stream) ||
       hipMemcpyAsync(h->at<long long>(L.dstep[last]), &h->step_staging, sizeof(long long), hipMemcpyHostToDevice,
                      h->stream) ||
+      // the fused step's completion marks count steps: a state restored at an earlier
+      // step than this context has run must not find them already reached
+      hipMemsetAsync(h->at<unsigned>(L.cdone), 0, (size_t)h->P.nblkL * sizeof(unsigned), h->stream) ||
       hipStreamSynchronize(h->stream))
     return LBM_EHIP;
   h->hist_count = 0;

@@ -67,3 +67,25 @@ def test_state_of_another_configuration_is_refused():
         a.write_state(bad)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("mode", ["one_launch", "two_launches"])
+def test_rewind_in_the_same_context(mode):
+    # restoring an earlier state into the context that ran past it, then running on,
+    # repeats the run bitwise (the fused step's per-tile completion marks count steps
+    # and must restart with the restored step)
+    from paper_1812_10375_amd.lbm import Lattice
+    lat = Lattice(_scenario("f32", mode))
+    lat.step(120)
+    ck = lat.checkpoint()
+    lat.step(200)
+    want = lat.observe()
+    want_f = {k: lat.read(k) for k in ("f", "T")}
+    lat.restore(ck)
+    lat.step(200)
+    got = lat.observe()
+    for k in want_f:
+        assert np.array_equal(lat.read(k), want_f[k]), k
+    for k in want:
+        assert got[k] == want[k], (k, got[k], want[k])
+    lat.close()
