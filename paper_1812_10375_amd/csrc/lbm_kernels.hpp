@@ -1245,29 +1245,44 @@ __global__ void __launch_bounds__(NT)
 __device__ __forceinline__ void finish_block(const KParams& P, const double* __restrict__ steps, int first,
                                              int count, int hist_cap, const double* __restrict__ partL_last,
                                              const double* __restrict__ pmin_last, DevDiag* __restrict__ diag) {
+  constexpr int FOLD_CHUNK = 256;  // steps staged in LDS at a time
   __shared__ double red[RED_SIZE];
+  __shared__ double sv[5 * FOLD_CHUNK];
   const int t = threadIdx.x;
+  // thread 0 folds the steps in order; the whole block first stages each chunk of them in
+  // LDS, so that the fold does not wait on one global load after another
+  DevDiag& dg = *diag;
+  double dE = 0, en = 0, Qb = 0, Qt = 0, Qs = 0, qb = 0, qs = 0, qm = 0, m2 = 0;
+  long long nr = 0;
   if (t == 0 && count > 0) {
-    // the running values stay in registers through the loop
-    DevDiag& dg = *diag;
-    double dE = dg.dE_cum, en = dg.energy, Qb = dg.Q_bottom_cum, Qt = dg.Q_top_cum, Qs = dg.Q_surface_cum;
-    double qb = dg.q_bottom, qs = dg.q_surface, qm = dg.q_mean, m2 = dg.q_m2;
-    long long nr = dg.nred;
-    for (int c = 0; c < count; ++c) {
-      const double* v = steps + 5 * ((first + c) % hist_cap);
-      dE += v[0];
-      en = v[1];
-      Qb += v[2];
-      Qt += v[3];
-      Qs += v[4];
-      qb = v[2] / P.nx;
-      qs = v[4] / P.nx;
-      nr += 1;
-      const double cnt = (double)nr, q = qb;
-      const double dl = q - qm;
-      qm += dl / cnt;
-      m2 += dl * (q - qm);
+    dE = dg.dE_cum; en = dg.energy; Qb = dg.Q_bottom_cum; Qt = dg.Q_top_cum; Qs = dg.Q_surface_cum;
+    qb = dg.q_bottom; qs = dg.q_surface; qm = dg.q_mean; m2 = dg.q_m2;
+    nr = dg.nred;
+  }
+  for (int base = 0; base < count; base += FOLD_CHUNK) {
+    const int nc = min(FOLD_CHUNK, count - base);
+    for (int i = t; i < 5 * nc; i += NT) sv[i] = steps[5 * ((first + base + i / 5) % hist_cap) + i % 5];
+    __syncthreads();
+    if (t == 0) {
+      for (int c = 0; c < nc; ++c) {
+        const double* v = sv + 5 * c;
+        dE += v[0];
+        en = v[1];
+        Qb += v[2];
+        Qt += v[3];
+        Qs += v[4];
+        qb = v[2] / P.nx;
+        qs = v[4] / P.nx;
+        nr += 1;
+        const double cnt = (double)nr, q = qb;
+        const double dl = q - qm;
+        qm += dl / cnt;
+        m2 += dl * (q - qm);
+      }
     }
+    __syncthreads();
+  }
+  if (t == 0 && count > 0) {
     dg.dE_cum = dE; dg.energy = en; dg.Q_bottom_cum = Qb; dg.Q_top_cum = Qt; dg.Q_surface_cum = Qs;
     dg.q_bottom = qb; dg.q_surface = qs; dg.q_mean = qm; dg.q_m2 = m2; dg.nred = nr;
   }
