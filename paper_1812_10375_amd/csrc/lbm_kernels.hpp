@@ -1248,6 +1248,7 @@ __device__ __forceinline__ void finish_block(const KParams& P, const double* __r
   constexpr int FOLD_CHUNK = 256;  // steps staged in LDS at a time
   __shared__ double red[RED_SIZE];
   __shared__ double sv[5 * FOLD_CHUNK];
+  __shared__ double sq[2 * FOLD_CHUNK];  // each step's q_bottom and q_surface (per unit length)
   const int t = threadIdx.x;
   // thread 0 folds the steps in order; the whole block first stages each chunk of them in
   // LDS, so that the fold does not wait on one global load after another
@@ -1261,7 +1262,12 @@ __device__ __forceinline__ void finish_block(const KParams& P, const double* __r
   }
   for (int base = 0; base < count; base += FOLD_CHUNK) {
     const int nc = min(FOLD_CHUNK, count - base);
-    for (int i = t; i < 5 * nc; i += NT) sv[i] = steps[5 * ((first + base + i / 5) % hist_cap) + i % 5];
+    for (int i = t; i < 5 * nc; i += NT) {
+      const double v = steps[5 * ((first + base + i / 5) % hist_cap) + i % 5];
+      sv[i] = v;
+      if (i % 5 == 2) sq[2 * (i / 5)] = v / P.nx;
+      if (i % 5 == 4) sq[2 * (i / 5) + 1] = v / P.nx;
+    }
     __syncthreads();
     if (t == 0) {
       for (int c = 0; c < nc; ++c) {
@@ -1271,8 +1277,8 @@ __device__ __forceinline__ void finish_block(const KParams& P, const double* __r
         Qb += v[2];
         Qt += v[3];
         Qs += v[4];
-        qb = v[2] / P.nx;
-        qs = v[4] / P.nx;
+        qb = sq[2 * c];
+        qs = sq[2 * c + 1];
         nr += 1;
         const double cnt = (double)nr, q = qb;
         const double dl = q - qm;
