@@ -115,3 +115,30 @@ def test_shear_wave_decay_gives_the_phase_viscosity(paper, rho, nu_key):
     rate = np.log(amps[1] / amps[2]) / 1000.0
     nu = rate / (np.pi / ny) ** 2
     assert nu == pytest.approx(paper[nu_key]["value"], rel=0.02)
+
+
+@pytest.mark.parametrize("frac", [0.1, 0.75])
+def test_shear_wave_decay_follows_the_linear_relaxation_time(frac):
+    # Between the phases tau varies linearly in rho (the reading of Sec. 3.1 taken here).
+    # A uniform fluid at a metastable density (vapour side, liquid side: outside the
+    # spinodal, so it stays uniform) decays a shear wave at nu = (tau(rho) - 1/2)/3.
+    nx, ny = 2, 48
+    rho = S.RHO_V + frac * (S.RHO_L - S.RHO_V)
+    y = np.arange(ny) + 0.5
+    ux = 1e-4 * np.sin(np.pi * y / ny)
+    sc = S.base_params(nx=nx, ny=ny, flags=ISO)
+    sc["rho0"] = np.full((ny, nx), rho)
+    sc["T0"] = np.full((ny, nx), S.T_SAT)
+    o = lbm.OracleSim(sc)
+    f = np.stack([np.stack([lbm.feq(rho, ux[j], 0.0) for _ in range(nx)]) for j in range(ny)])
+    o.set_field("f", np.transpose(f, (2, 0, 1)))
+    amps = []
+    for _ in range(3):
+        o.step(1000)
+        u = o.field("ux")[:, 0]
+        amps.append((u * np.sin(np.pi * y / ny)).sum() / (np.sin(np.pi * y / ny) ** 2).sum())
+    r = o.field("rho")
+    assert r.max() - r.min() < 1e-4 * rho
+    nu = np.log(amps[1] / amps[2]) / 1000.0 / (np.pi / ny) ** 2
+    tau = sc["tau_v"] + (sc["tau_l"] - sc["tau_v"]) * frac
+    assert nu == pytest.approx((tau - 0.5) / 3.0, rel=5e-3)
