@@ -108,3 +108,22 @@ def test_batch_rejects_incompatible_domains():
         rc = L.lbm_batch_init(bad.cfgs, 2, fake, 1 << 30, None, bad.rho0, bad.T0, C.byref(h))
         assert rc == -1 and not h.value, change
     assert L.lbm_batch_workspace_bytes(good.cfgs, 0) == 0
+
+
+def test_autotuners_reject_bad_arguments_before_any_device_work():
+    L = lbm.library()
+    a = S.film_evaporation(nx=16, ny=16, film=4, precision="f32")
+    inp = lbm._BatchInputs([a, a])
+    need = L.lbm_batch_workspace_bytes(inp.cfgs, 2)
+    fake = C.c_void_p(1 << 20)  # never dereferenced: the calls fail before any device work
+    rows, flags, ms = (C.c_int32 * 2)(), (C.c_uint32 * 2)(), C.c_double()
+    r1, ms1 = C.c_int(), C.c_double()
+    # missing outputs, no steps, a workspace too small, incompatible domains
+    assert L.lbm_autotune(inp.cfgs, 2, fake, need, None, inp.rho0, inp.T0, 5, None, flags, C.byref(ms)) == -1
+    assert L.lbm_autotune(inp.cfgs, 2, fake, need, None, inp.rho0, inp.T0, 0, rows, flags, C.byref(ms)) == -1
+    assert L.lbm_autotune(inp.cfgs, 2, fake, need - 1, None, inp.rho0, inp.T0, 5, rows, flags, C.byref(ms)) == -2
+    assert L.lbm_autotune_tile_rows(inp.cfgs, 2, fake, need, None, inp.rho0, inp.T0, 5, None, C.byref(ms1)) == -1
+    bad = lbm._BatchInputs([a, dict(a, precision="f64")])
+    assert L.lbm_autotune(bad.cfgs, 2, fake, 1 << 30, None, bad.rho0, bad.T0, 5, rows, flags, C.byref(ms)) == -1
+    assert L.lbm_autotune_tile_rows(bad.cfgs, 2, fake, 1 << 30, None, bad.rho0, bad.T0, 5, C.byref(r1),
+                                    C.byref(ms1)) == -1
