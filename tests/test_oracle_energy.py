@@ -196,3 +196,48 @@ def test_steady_flux_difference_isotropic(paper, relaxed40):
     # Sec. 3.2: about 0.18 with the isotropic central scheme (Eq. 20-21)
     d = _steady_flux_difference(relaxed40, EXACT + ("diff_isotropic",))
     assert d == pytest.approx(paper["flux_difference_isotropic"]["value"], abs=0.01)
+
+
+@pytest.mark.parametrize("top_bc", ["wall", "const_pressure", "convective"])
+def test_divergence_next_to_walls_and_an_open_top(top_bc):
+    # Velocities at solid nodes are zero and an open top is zero-gradient (the readings
+    # of the gradients at walls): u_y = c (y + 1), linear and zero at the solid row below
+    # the fluid, has the exact divergence c by Eq. 19 on every row up to the one below
+    # the top; on the top row the ghost above holds 0 under a wall, u_y(top) under an
+    # open top, and the y-only field's stencil reduces to (u(y+1) - u(y-1)) / 2.
+    rng = np.random.default_rng(4)
+    nx, ny = 5, 9
+    rho = rng.uniform(0.5, 6.0, (ny, nx))
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    c = 2.0e-3
+    Y = rng.uniform(0.09, 0.1, (ny, nx))
+    a, sc = _sim(nx, ny, rho=rho, flags=("no_advection",), top_bc=top_bc)
+    b, _ = _sim(nx, ny, rho=rho, flags=("no_advection", "no_latent"), top_bc=top_bc)
+    uy = c * (y + 1.0)
+    for o in (a, b):
+        o.set_field("ux", np.zeros((ny, nx)))
+        o.set_field("uy", uy)
+    lat = a.energy_rhs(Y)[0] - b.energy_rhs(Y)[0]
+    coef = -(Y / (rho * sc["cv"])) * eos.dp_dT(rho, Y, S.OMEGA)
+    assert lat[:-1] == pytest.approx(coef[:-1] * c, rel=1e-10)
+    above = 0.0 if top_bc == "wall" else uy[-1]
+    assert lat[-1] == pytest.approx(coef[-1] * (above - uy[-2]) / 2.0, rel=1e-10)
+
+
+def test_advection_gradient_uses_the_dirichlet_ghost_values():
+    # A Dirichlet value sits on a ghost node one spacing beyond the last temperature row
+    # (the reading of the thermal boundaries).  A temperature linear in y whose ghost
+    # values continue the line has the exact gradient by Eq. 19 on every row, so a uniform
+    # upward velocity U advects it at -U s everywhere, the rows next to both walls included.
+    nx, ny = 5, 9
+    s, U, T0 = 3e-4, 1e-3, 0.062
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    T = T0 + s * (y + 1.0)
+    kw = dict(T_bottom=T0, T_top=T0 + s * (ny + 1.0), bottom_tbc="dirichlet", top_tbc="dirichlet")
+    a, _ = _sim(nx, ny, T=T, flags=("no_latent",), **kw)
+    b, _ = _sim(nx, ny, T=T, flags=("no_latent", "no_advection"), **kw)
+    for o in (a, b):
+        o.set_field("ux", np.zeros((ny, nx)))
+        o.set_field("uy", np.full((ny, nx), U))
+    adv = a.energy_rhs(T)[0] - b.energy_rhs(T)[0]
+    assert adv == pytest.approx(np.full((ny, nx), -U * s), rel=1e-9)
