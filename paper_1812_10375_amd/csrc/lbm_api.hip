@@ -649,6 +649,17 @@ namespace {
 
 size_t batch_table_bytes(int n) { return align_up((size_t)n * sizeof(lbmk::DomainDev)); }
 
+// the tile-to-domain maps of a batch (collide tiles, then energy tiles; the energy tile
+// count bounded as in a domain's layout)
+size_t batch_map_bytes(const lbm_config* cfgs, int n) {
+  size_t tiles = 0;
+  for (int i = 0; i < n; ++i) {
+    const Grids g = grids(&cfgs[i], 0);
+    tiles += (size_t)g.ntxL * g.ntyL + (size_t)g.ntxE * g.ntyE;
+  }
+  return align_up(tiles * sizeof(int));
+}
+
 bool batch_compatible(const lbm_config* cfgs, int n) {
   if (!cfgs || n < 1) return false;
   for (int i = 0; i < n; ++i) {
@@ -774,7 +785,7 @@ extern "C" {
 
 size_t lbm_batch_workspace_bytes(const lbm_config* cfgs, int n) {
   if (!batch_compatible(cfgs, n)) return 0;
-  size_t total = batch_table_bytes(n);
+  size_t total = batch_table_bytes(n) + batch_map_bytes(cfgs, n);
   for (int i = 0; i < n; ++i) total += align_up(lbm_workspace_bytes(&cfgs[i]));
   return total;
 }
@@ -792,7 +803,8 @@ int lbm_batch_init(const lbm_config* cfgs, int n, void* d_workspace, size_t ws_b
   b->stream = reinterpret_cast<hipStream_t>(hip_stream);
   char* base = reinterpret_cast<char*>(d_workspace);
   b->table = reinterpret_cast<lbmk::DomainDev*>(base);
-  size_t off = batch_table_bytes(n);
+  b->domL = reinterpret_cast<int*>(base + batch_table_bytes(n));
+  size_t off = batch_table_bytes(n) + batch_map_bytes(cfgs, n);
   std::vector<lbmk::DomainDev> tab(n);
   int tL = 0, tE = 0;
   for (int i = 0; i < n; ++i) {
@@ -820,7 +832,15 @@ int lbm_batch_init(const lbm_config* cfgs, int n, void* d_workspace, size_t ws_b
   }
   b->nblkL = tL;
   b->nblkE = tE;
+  b->domE = b->domL + tL;
+  std::vector<int> dom((size_t)tL + tE);
+  for (int i = 0; i < n; ++i) {
+    std::fill(dom.begin() + tab[i].tile0L, dom.begin() + tab[i].tile0L + tab[i].P.nblkL, i);
+    std::fill(dom.begin() + tL + tab[i].tile0E, dom.begin() + tL + tab[i].tile0E + tab[i].P.nblkE, i);
+  }
   if (hipMemcpyAsync(b->table, tab.data(), n * sizeof(lbmk::DomainDev), hipMemcpyHostToDevice, b->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(b->domL, dom.data(), dom.size() * sizeof(int), hipMemcpyHostToDevice, b->stream) !=
           hipSuccess ||
       hipStreamSynchronize(b->stream) != hipSuccess) {
     lbm_batch_destroy(b);

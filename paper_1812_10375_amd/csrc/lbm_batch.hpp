@@ -1,6 +1,6 @@
 // lbm_batch.hpp -- batched step over independent domains.  One launch covers the tiles
-// of every domain of a batch: a workgroup takes global tile g (XCD-aware order), finds
-// its domain in the device table by binary search over the first-tile offsets, and runs
+// of every domain of a batch: a workgroup takes global tile g (XCD-aware order), reads
+// its domain from the batch's tile-to-domain map (one scalar load), and runs
 // the same per-tile code as the single-domain kernels with that domain's parameters and
 // buffers.  All domains share the step parity, so every argument of a launch depends
 // only on the parity and the diagnostics history slot.
@@ -10,24 +10,11 @@
 
 namespace lbmk {
 
-// Largest d with first(d) <= g (first(0) = 0, increasing).
-template <bool ENERGY>
-__device__ __forceinline__ int batch_domain(const DomainDev* __restrict__ tab, int ndom, int g) {
-  int lo = 0, hi = ndom - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const int first = ENERGY ? tab[mid].tile0E : tab[mid].tile0L;
-    if (first <= g) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 template <typename real, int TY, int NW>
 __global__ void __launch_bounds__(NW * 64)
-    k_collide_batch(const DomainDev* __restrict__ tab, int ndom, int fcur, int tcur, int cur) {
+    k_collide_batch(const DomainDev* __restrict__ tab, const int* __restrict__ domL, int fcur, int tcur, int cur) {
   const int g = xcd_tile(blockIdx.x, gridDim.x);
-  const int d = batch_domain<false>(tab, ndom, g);
+  const int d = domL[g];
   const DomainDev& D = tab[d];
   const Layout& L = D.L;
   char* ws = D.ws;
@@ -63,11 +50,11 @@ __device__ __forceinline__ bool batch_outlet(const DomainDev* __restrict__ tab, 
 // FP32 register-row kernel
 template <int NW, int B, int WPE>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
-    k_energy_rows_batch(const DomainDev* __restrict__ tab, int ndom, int fpost, int tcur, int cur,
-                        int hslot, int sub, double dtd) {
+    k_energy_rows_batch(const DomainDev* __restrict__ tab, int ndom, const int* __restrict__ domE, int fpost,
+                        int tcur, int cur, int hslot, int sub, double dtd) {
   if (batch_outlet<float, NW>(tab, ndom, fpost, cur, sub)) return;
   const int g = xcd_tile_edges_first(blockIdx.x - ndom, gridDim.x - ndom);
-  const int d = batch_domain<true>(tab, ndom, g);
+  const int d = domE[g];
   const DomainDev& D = tab[d];
   const Layout& L = D.L;
   char* ws = D.ws;
@@ -82,11 +69,11 @@ __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WP
 // LDS kernel (FP64, or the isotropic scheme)
 template <typename real, bool ISO, int NW, int HMAX>
 __global__ void __launch_bounds__(NW * 64)
-    k_energy_batch(const DomainDev* __restrict__ tab, int ndom, int fpost, int tcur, int cur, int hslot,
-                   int sub, double dtd) {
+    k_energy_batch(const DomainDev* __restrict__ tab, int ndom, const int* __restrict__ domE, int fpost, int tcur,
+                   int cur, int hslot, int sub, double dtd) {
   if (batch_outlet<real, NW>(tab, ndom, fpost, cur, sub)) return;
   const int g = xcd_tile_edges_first(blockIdx.x - ndom, gridDim.x - ndom);
-  const int d = batch_domain<true>(tab, ndom, g);
+  const int d = domE[g];
   const DomainDev& D = tab[d];
   const Layout& L = D.L;
   char* ws = D.ws;

@@ -62,6 +62,8 @@ struct lbm_batch {
   std::vector<lbm_ctx*> dom;  // per-domain contexts; the batch keeps their bookkeeping in step
   hipStream_t stream;
   lbmk::DomainDev* table;     // device table, first in the workspace
+  int* domL;                  // domain of every collide tile of the batch (device)
+  int* domE;                  // domain of every energy tile of the batch (device)
   int nblkL, nblkE;           // collide and energy tiles over all domains
 };
 

@@ -136,18 +136,18 @@ void batch_step_once(lbm_batch* b) {
   const int hslot = (h0->hist_first + h0->hist_count) % HIST;
   const bool iso = (h0->cfg.flags & LBM_DIFF_ISOTROPIC) != 0;
   hipLaunchKernelGGL((lbmk::k_collide_batch<real, f64 ? TY_F64 : TY_F32, NWC>), dim3(b->nblkL), dim3(NWC * 64), 0,
-                     b->stream, b->table, n, fcur, tcur, cur);
+                     b->stream, b->table, b->domL, fcur, tcur, cur);
   const double dt = 1.0 / h0->cfg.n_sub;
   for (int sub = 0; sub < h0->cfg.n_sub; ++sub) {
     if (iso)
       hipLaunchKernelGGL((lbmk::k_energy_batch<real, true, E_NW, E_HMAX>), dim3(b->nblkE + n), dim3(E_NW * 64), 0,
-                         b->stream, b->table, n, 1 - fcur, tcur, cur, hslot, sub, dt);
+                         b->stream, b->table, n, b->domE, 1 - fcur, tcur, cur, hslot, sub, dt);
     else if constexpr (f64)
       hipLaunchKernelGGL((lbmk::k_energy_batch<real, false, E_NW, E_HMAX>), dim3(b->nblkE + n), dim3(E_NW * 64), 0,
-                         b->stream, b->table, n, 1 - fcur, tcur, cur, hslot, sub, dt);
+                         b->stream, b->table, n, b->domE, 1 - fcur, tcur, cur, hslot, sub, dt);
     else
       hipLaunchKernelGGL((lbmk::k_energy_rows_batch<E_RNW, E_BAND, E_RWPE>), dim3(b->nblkE + n), dim3(E_RNW * 64), 0,
-                         b->stream, b->table, n, 1 - fcur, tcur, cur, hslot, sub, dt);
+                         b->stream, b->table, n, b->domE, 1 - fcur, tcur, cur, hslot, sub, dt);
     tcur = 1 - tcur;
   }
   for (lbm_ctx* h : b->dom) {
