@@ -272,7 +272,7 @@ def boiling_curve(n_query=10000, cases=((512, 0.05),)):
     whole run): the plain per-run GPU form (one single-domain run per point) against
     batched runs of the method plus the surrogate ensemble (trained on batched runs,
     falling back to batched runs where its members' spread of log q, or the out-of-bag
-    error of the nearest training runs, exceeds the threshold), judged against 16
+    error of the nearest training runs, exceeds the threshold), measured against 16
     held-out plain runs and, for a statistically useful average, 128 validation runs.
     The first case (512 training runs, 5%) is the configured one; a second case, when
     given, adds training runs (--boiling-curve-more: 1024 runs)."""

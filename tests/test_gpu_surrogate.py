@@ -12,7 +12,7 @@ members' spread, the out-of-bag error of the nearest training runs).
 * Trained on 1024 runs (the same 512 and 512 more), the answers are closer still.
 
 Errors are measured on 128 validation runs (a fallback point is the run itself, exact)
-and reported for the 16 held-out runs of the configured judge as well; the sixteen are
+and reported for the 16 held-out runs of the configured reference as well; the sixteen are
 too few for an average that one point near the boiling crisis cannot move by 1%."""
 import numpy as np
 import pytest
@@ -80,7 +80,7 @@ def _case(R, n_train, threshold=0.05, n_query=1000):
     (_, fall), t_query = SG.timed(SG.boiling_curve, sur, Xq, R["proto"], threshold)
     t_data = R["t_data"][0 if n_train == 512 else 1]
     gain = N_QUERY * R["t_single"] / (t_data + t_train + t_query * N_QUERY / n_query)
-    # the configured judge: 16 held-out plain runs (a fallback point is the run itself)
+    # the configured reference: 16 held-out plain runs (a fallback point is the run itself)
     vh, fh = SG.boiling_curve(sur, R["Xh"], R["proto"], threshold)
     err_h = np.abs(vh[:, 0] / R["Yh"][:, 0] - 1.0)
     out = dict(kept_err=err_v[kept].mean(), kept_max=err_v[kept].max(), kept_frac=kept.mean(),
