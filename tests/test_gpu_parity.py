@@ -233,3 +233,33 @@ def test_fp32_energy_substeps_and_flux_bottom():
 def test_fp32_degenerate_and_ragged_shapes(nx, ny, nh):
     sc = S.pool_boiling(nx=nx, ny=ny, heater_rows=nh, n_sites=0, seed=1, precision="f32")
     _check32(sc, 50)
+
+
+def test_fp32_isotropic_comparison_scheme():
+    # the comparison scheme of Eq. 20-21 in FP32 (the LDS energy kernel), across a flat
+    # interface between Dirichlet walls
+    sc = S.interface_conduction(nx=8, ny=64, steps=200)
+    sc["flags"] = ("freeze_eos_T", "no_advection", "no_latent", "diff_isotropic")
+    sc["precision"] = "f32"
+    _check32_heat(sc, 200)
+
+
+@pytest.mark.parametrize("isotropic", [False, True])
+def test_fp32_flux_driven_film_with_a_conductive_wall(isotropic):
+    # the Sec. 3.3 film at its paper size in FP32: 20-row wall at three times the
+    # liquid's conductivity, heat flux through the bottom, constant-pressure top, five
+    # energy sub-steps per LB step (Eq. 27), both diffusion schemes.  The heat through
+    # the bottom is q per unit length and step in both.  The stored-energy change sums
+    # rho c_v dT over the run; with the wall's heat capacity large against the heat let
+    # in, its FP32 difference is bounded by the fields' instead: about sum(rho c_v) max|dT|.
+    sc = S.film_evaporation_flux(3.0, 2e-4, precision="f32", isotropic=isotropic)
+    steps = 300
+    res, e = _check32(sc, steps)
+    og, oo = res["gpu_obs"], res["orc_obs"]
+    assert og["Q_bottom_cum"] == pytest.approx(2e-4 * sc["nx"] * steps, rel=1e-6)
+    assert og["Q_bottom_cum"] == pytest.approx(oo["Q_bottom_cum"], rel=1e-6)
+    cap = sc["rho_w"] * sc["cv_w"] * sc["heater_rows"] * sc["nx"] + (res["rho"][1] * sc["cv"]).sum()
+    dT = np.abs(res["T"][0] - res["T"][1]).max()
+    log("[parity] dE_cum GPU %.6f oracle %.6f; bound %.6f" % (og["dE_cum"], oo["dE_cum"], 2 * cap * dT))
+    # (twice the bound: rho of each step, not only the last, weighs the increments)
+    assert abs(og["dE_cum"] - oo["dE_cum"]) <= 2 * cap * dT
