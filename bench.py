@@ -224,7 +224,20 @@ def two_launch_reference(sc, steps, warmup):
     torch.cuda.synchronize()
     kt = lat.kernel_times()
     lat.close()
-    return {"ms_per_step": ms, "kernels_ms": {k: v[0] / v[1] for k, v in kt.items() if v[1]}}
+    per = {k: v[0] / v[1] for k, v in kt.items() if v[1]}
+    out = {"ms_per_step": ms, "kernels_ms": per}
+    if "collide" in per and "energy" in per:
+        # each kernel against its own roofline: the collide kernel's 72 B per fluid node
+        # against HBM, the energy kernel's counted flops against the FP32 vector peak
+        # (its bound; the non-packed rate is half of that peak)
+        cb = algorithmic_bytes(sc) / (per["collide"] * 1e-3) / 1e9
+        ef = algorithmic_flops(sc) / (per["energy"] * 1e-3) / 1e12
+        out["rooflines"] = {
+            "collide": {"bound": "hbm", "achieved": cb, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                        "frac": cb / HBM_PEAK_GBPS},
+            "energy": {"bound": "alu", "achieved": ef, "peak": FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                       "frac": ef / FP32_VECTOR_TFLOPS}}
+    return out
 
 
 def hbm_resident(n=4096, steps=100, warmup=10):
